@@ -1,0 +1,162 @@
+/*
+ * r3d.h - C ABI of the R3DSP per-frame hot path on AMD Instinct MI355X (gfx950).
+ *
+ * R3DSP is the online single-photon lidar reconstruction of Legros et al.,
+ * "Robust 3D reconstruction of dynamic scenes from single-photon lidar using
+ * Beta-divergences" (arXiv:2004.09211). For every pixel of a frame the
+ * library
+ *   (a1) histograms the photon times of arrival (ToAs) of the pixel (Sec. II-A,
+ *        discrete Poisson model),
+ *   (a3) evaluates the beta-divergence log pseudo-likelihood on the depth grid,
+ *        ell(d) = (beta+1)/beta * sum_j irf[j]^beta * z[d - c + j]
+ *        (Sec. II-B, eq. beta_div2 and its histogram form),
+ *   (a4) builds the spatio-temporal prior: a Gaussian mixture over the 3x3
+ *        neighbourhood of the previous frame convolved with a Gaussian random
+ *        walk, with flat components for undetected or out-of-frame neighbours
+ *        (Sec. III-A, eq. predict),
+ *   (a5) normalises the pseudo-posterior on the grid and extracts its argmax,
+ *        mean and variance (Sec. II-C, eq. approx_post; Sec. III-A, eq. KL_div),
+ *   (a6) writes the new Gaussian state and the depth (NaN when undetected),
+ *   (a7) estimates background and reflectivity (Sec. II-E, eq. lik_bg_poisson),
+ * and the prior presence probability of the next frame (Sec. III-B,
+ * eq. prior_detect), i.e. one iteration of Algorithm 1 for every pixel.
+ *
+ * Units: every time and depth is in histogram bins. A surface at depth d puts
+ * tap j of the IRF into bin t = d - c + j, c being the tap of the IRF maximum.
+ * The depth grid is d = d_lo .. d_lo + D - 1; bins outside [0, T) count zero.
+ *
+ * Memory: every array argument of a step is DEVICE memory owned by the
+ * caller; the library keeps no caller pointer past the call. The library owns
+ * only its context (the uploaded IRF, its powers and an error word).
+ * Streams: calls enqueue on the given stream (a hipStream_t passed as void*,
+ * NULL = the default stream) and never synchronise, except r3d_create,
+ * r3d_last_device_status and r3d_destroy. A context is used by one stream at a
+ * time.
+ * Errors: parameter and shape errors are returned synchronously before any
+ * launch. Data-dependent faults found by a kernel (a ToA outside [0, T), an
+ * fp16 count above 2048 or negative) set the context's device error word, read
+ * back by r3d_last_device_status; the affected outputs are then undefined.
+ */
+#ifndef R3D_H
+#define R3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    R3D_OK = 0,
+    R3D_EINVAL = -1,        /* bad parameter, shape or NULL pointer             */
+    R3D_ERANGE = -2,        /* a ToA outside [0, T) (device-detected)           */
+    R3D_EOVERFLOW = -3,     /* an fp16 count > 2048 or < 0 (device-detected)    */
+    R3D_ENOMEM = -4,        /* device allocation failed                         */
+    R3D_EHIP = -5,          /* a HIP runtime call failed                        */
+    R3D_EUNSUPPORTED = -6   /* size or option outside what the kernels support  */
+} r3d_status;
+
+/* How the cost correlation (a3) is evaluated.
+ * R3D_FP32: fp32 vector FMAs (the plain form).
+ * R3D_FP16_MFMA: banded Toeplitz contraction on the matrix cores with fp16
+ *   counts and fp16 irf^beta, fp32 accumulation (histogram input only).
+ * R3D_FP16X2_MFMA: as above with irf^beta split into an fp16 high part and an
+ *   fp16 low part (two contractions), about 22 significant bits. */
+typedef enum {
+    R3D_FP32 = 0,
+    R3D_FP16_MFMA = 1,
+    R3D_FP16X2_MFMA = 2
+} r3d_precision;
+
+typedef struct r3d_ctx r3d_ctx;
+
+/* Model parameters (Algorithm 1 fixed inputs plus the observation model). */
+typedef struct {
+    int32_t rows, cols;     /* frame size, P = rows*cols, pixel p = row*cols + col */
+    int32_t T;              /* timing bins per histogram, 1 <= T <= 32767          */
+    int32_t d_lo, D;        /* depth grid d_lo .. d_lo+D-1, 1 <= D <= 32768        */
+    double  d_min, d_max;   /* bounds of the flat prior component, d_max > d_min   */
+    double  beta;           /* beta-divergence parameter, beta > 0                 */
+    int32_t W, c;           /* IRF taps (1..256) and tap of its maximum (0..W-1)   */
+    const double *irf;      /* HOST pointer, W non-negative taps, used verbatim    */
+    double  nu[9];          /* 3x3 mixture weights, row-major, centre nu[4], >= 0  */
+    double  sigma_rw2;      /* random-walk variance, > 0                           */
+    int32_t precision;      /* r3d_precision                                       */
+} r3d_params;
+
+/* Filter state of one frame, device arrays of P floats each (caller-owned):
+ * q = N(m, v) per pixel, presence probability pi, background level b. */
+typedef struct {
+    float *m, *v, *pi, *b;
+} r3d_state;
+
+/* Per-pixel outputs of one frame, device arrays of P elements (caller-owned).
+ * Any pointer may be NULL to skip that output. depth is the posterior mean
+ * where pi > 0.5 and NaN elsewhere; var the posterior variance; argmax the
+ * grid depth of the pseudo-posterior maximum (lowest on ties); intensity and
+ * background the reflectivity / background estimates; pi0_next the prior
+ * presence probability of the next frame. */
+typedef struct {
+    float   *depth, *var, *intensity, *background, *pi0_next;
+    int32_t *argmax;
+} r3d_out;
+
+/* Create a context on the current HIP device: validates the parameters,
+ * uploads irf and irf^beta. Synchronous. Returns R3D_EINVAL on a bad
+ * parameter (beta <= 0, sigma_rw2 <= 0, W out of range, c outside [0, W),
+ * negative or all-zero irf or nu, d_max <= d_min, empty sizes). */
+r3d_status r3d_create(const r3d_params *params, r3d_ctx **out);
+
+/* Destroy a context (synchronises the device first). NULL is ignored. */
+void r3d_destroy(r3d_ctx *ctx);
+
+/* Initial state of Algorithm 1 (left open by the paper): every pixel flat,
+ * m = (d_min+d_max)/2, v = (d_max-d_min)^2/12, pi = 0.5, b = 0. */
+r3d_status r3d_state_init(r3d_ctx *ctx, const r3d_state *st, void *stream);
+
+/* a1 alone: per-pixel photon-count histogram of a CSR photon list, written as
+ * fp16 [P][T] (IEEE binary16 bits). row_ptr: int32[P+1], non-decreasing,
+ * row_ptr[0] = 0; toa: int16[row_ptr[P]], any order inside a pixel. Counts
+ * are exact up to 2048; a larger count sets R3D_EOVERFLOW, a ToA outside
+ * [0, T) sets R3D_ERANGE (device error word). */
+r3d_status r3d_histogram(r3d_ctx *ctx, const int32_t *row_ptr, const int16_t *toa,
+                         uint16_t *hist, void *stream);
+
+/* a3 alone, for inspection and tests: ell(d) for npix pixels of an fp16
+ * histogram [npix][T], written as float [npix][D] in natural-log units, with
+ * the context's precision. */
+r3d_status r3d_cost(r3d_ctx *ctx, const uint16_t *hist, int32_t npix, float *ell,
+                    void *stream);
+
+/* One frame of Algorithm 1 from CSR photon lists (a1..a7 fused).
+ * pi_in: float[P] presence probabilities of this frame from the caller's
+ * detector, or NULL (every pixel detected, pi = 1). faulty: uint8[P] mask of
+ * pixels without observations, or NULL; a faulty pixel keeps its prior as
+ * pseudo-posterior and gets pi = 0.5 (Sec. III-B). prev is read, next is
+ * written; they must not alias. Only R3D_FP32 evaluates photon lists. */
+r3d_status r3d_step_csr(r3d_ctx *ctx, const int32_t *row_ptr, const int16_t *toa,
+                        const float *pi_in, const uint8_t *faulty,
+                        const r3d_state *prev, const r3d_state *next,
+                        const r3d_out *out, void *stream);
+
+/* One frame of Algorithm 1 from fp16 histograms [P][T] (IEEE binary16 bits,
+ * integer counts 0..2048). Same semantics as r3d_step_csr; the cost is
+ * evaluated with the context's precision. */
+r3d_status r3d_step_hist(r3d_ctx *ctx, const uint16_t *hist,
+                         const float *pi_in, const uint8_t *faulty,
+                         const r3d_state *prev, const r3d_state *next,
+                         const r3d_out *out, void *stream);
+
+/* Synchronise the stream, then read and clear the device error word:
+ * R3D_OK, R3D_ERANGE or R3D_EOVERFLOW (the first kind recorded). */
+r3d_status r3d_last_device_status(r3d_ctx *ctx, void *stream);
+
+/* Static description of a status code. */
+const char *r3d_status_string(r3d_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* R3D_H */

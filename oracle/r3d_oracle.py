@@ -199,6 +199,8 @@ def prior_components(model: Model, state: State, pixels: np.ndarray):
         rr, cc = r + dr, col + dc
         inside = (rr >= 0) & (rr < model.rows) & (cc >= 0) & (cc < model.cols)
         q = np.where(inside, rr * model.cols + cc, 0)
+        if np.any(inside & ~np.isfinite(state.pi[q])):
+            raise ValueError("neighbour state needed but not available")
         det = inside & (state.pi[q] > 0.5)
         if np.any(det & ~(np.isfinite(state.m[q]) & np.isfinite(state.v[q]))):
             raise ValueError("neighbour state needed but not available")

@@ -1,0 +1,301 @@
+// Plain fp32 kernels: IRF preparation, state initialisation, photon
+// histogramming (a1), the cost alone (a3) and the fused per-frame step
+// (a1..a7) with one wavefront per pixel.
+//
+// The fused step keeps the pixel's histogram and its log pseudo-posterior on
+// the depth grid in LDS: lanes own depth bins d = d_lo + lane + 64 i, the cost
+// correlation reads the histogram window from LDS, the argmax and the
+// moments are wavefront reductions, and lane 0 writes the pixel's outputs.
+#include "r3d_device.hpp"
+
+namespace r3d {
+
+// a2: h = irf^beta (Sec. II-B), also split into fp16 high and scaled low
+// parts for the matrix-core contraction: h ~ hi + lo / 2048.
+__global__ void k_prepare_irf(const double* __restrict__ irf, int W, double beta,
+                              float* __restrict__ h, float* __restrict__ irf32,
+                              _Float16* __restrict__ hi, _Float16* __restrict__ lo) {
+  for (int j = threadIdx.x; j < W; j += blockDim.x) {
+    const double x = irf[j];
+    const double hv = x > 0.0 ? pow(x, beta) : 0.0;
+    h[j] = (float)hv;
+    irf32[j] = (float)x;
+    const _Float16 a = (_Float16)hv;
+    hi[j] = a;
+    lo[j] = (_Float16)((hv - (double)a) * 2048.0);
+  }
+}
+
+hipError_t launch_prepare_irf(const double* irf_dev, int W, double beta, float* h, float* irf,
+                              _Float16* hi, _Float16* lo, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare_irf, dim3(1), dim3(256), 0, s, irf_dev, W, beta, h, irf, hi, lo);
+  return hipGetLastError();
+}
+
+__global__ void k_state_init(int P, float m, float v, float* __restrict__ sm,
+                             float* __restrict__ sv, float* __restrict__ spi,
+                             float* __restrict__ sb) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+    sm[p] = m;
+    sv[p] = v;
+    spi[p] = 0.5f;
+    sb[p] = 0.f;
+  }
+}
+
+hipError_t launch_state_init(const DevModel& M, float* sm, float* sv, float* spi, float* sb,
+                             hipStream_t s) {
+  const int blocks = (M.P + 255) / 256 < 4096 ? (M.P + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(256), 0, s, M.P, M.m_flat, M.v_flat, sm,
+                     sv, spi, sb);
+  return hipGetLastError();
+}
+
+// waves per block so that nw * per_wave_bytes + fixed_bytes fits in 64 KiB
+static int waves_for(size_t per_wave_bytes, size_t fixed_bytes) {
+  const size_t cap = 65536;
+  if (per_wave_bytes + fixed_bytes > cap) return 0;
+  size_t nw = (cap - fixed_bytes) / per_wave_bytes;
+  return nw >= 4 ? 4 : (int)nw;
+}
+
+// ---------------------------------------------------------------- a1
+// One wavefront per pixel: integer LDS atomics (order-independent, hence
+// bit-exact), then the counts are written as fp16.
+__global__ void __launch_bounds__(256) k_histogram(DevModel M, const int32_t* __restrict__ row_ptr,
+                                                   const int16_t* __restrict__ toa,
+                                                   uint16_t* __restrict__ out) {
+  extern __shared__ unsigned smem_u[];
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned* hist = smem_u + wave * M.T;
+  const int p = blockIdx.x * nw + wave;
+  const bool active = p < M.P;
+  for (int t = lane; t < M.T; t += 64) hist[t] = 0u;
+  __syncthreads();
+  unsigned bad = 0;
+  if (active) {
+    const int b = row_ptr[p], e = row_ptr[p + 1];
+    if (e < b) bad |= kErrRange;
+    for (int k = b + lane; k < e; k += 64) {
+      const int t = toa[k];
+      if ((unsigned)t < (unsigned)M.T)
+        atomicAdd(&hist[t], 1u);
+      else
+        bad |= kErrRange;
+    }
+  }
+  __syncthreads();
+  if (active) {
+    uint16_t* row = out + (size_t)p * M.T;
+    for (int t = lane; t < M.T; t += 64) {
+      const unsigned n = hist[t];
+      if (n > 2048u) bad |= kErrOverflow;
+      const _Float16 h = (_Float16)(float)n;
+      uint16_t bits;
+      __builtin_memcpy(&bits, &h, 2);
+      row[t] = bits;
+    }
+  }
+  if (bad) atomicOr(M.err, bad);
+}
+
+hipError_t launch_histogram(const DevModel& M, const int32_t* row_ptr, const int16_t* toa,
+                            uint16_t* hist, hipStream_t s) {
+  const int nw = waves_for((size_t)M.T * 4, 0);
+  if (nw == 0) return hipErrorInvalidValue;
+  const dim3 grid((M.P + nw - 1) / nw);
+  hipLaunchKernelGGL(k_histogram, grid, dim3(64 * nw), (size_t)nw * M.T * 4, s, M, row_ptr, toa,
+                     hist);
+  return hipGetLastError();
+}
+
+// Load an fp16 histogram row into LDS as integers; returns the photon count
+// K (sum over the wavefront) and flags counts that are negative, above 2048
+// or fractional.
+__device__ __forceinline__ float load_hist_row(const DevModel& M, const uint16_t* __restrict__ row,
+                                               unsigned* hist, int lane, unsigned& bad) {
+  float ks = 0.f;
+  for (int t = lane; t < M.T; t += 64) {
+    const float x = half_bits_to_float(row[t]);
+    const bool ok = x >= 0.f && x <= kMaxFp16Count && x == truncf(x);
+    if (!ok) bad |= kErrOverflow;
+    const float xc = ok ? x : 0.f;
+    hist[t] = (unsigned)xc;
+    ks += xc;
+  }
+  return group_sum<1, 32>(ks);
+}
+
+// cost at grid point d from the LDS histogram: sum_j h[j] z[d - c + j]
+__device__ __forceinline__ float cost_at(const DevModel& M, const float* sh_h,
+                                         const unsigned* hist, int d) {
+  const int t0 = d - M.c;
+  const int jlo = t0 < 0 ? -t0 : 0;
+  const int jhi = (M.T - t0) < M.W ? (M.T - t0) : M.W;
+  float ell = 0.f;
+  for (int j = jlo; j < jhi; ++j) ell = fmaf(sh_h[j], (float)hist[t0 + j], ell);
+  return ell;
+}
+
+// ---------------------------------------------------------------- a3 alone
+__global__ void __launch_bounds__(256) k_cost_plain(DevModel M, const uint16_t* __restrict__ hist_in,
+                                                    int npix, float* __restrict__ ell_out) {
+  extern __shared__ float smem_f[];
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* sh_h = smem_f;
+  unsigned* hist = reinterpret_cast<unsigned*>(smem_f + M.W) + wave * M.T;
+  const int p = blockIdx.x * nw + wave;
+  for (int i = threadIdx.x; i < M.W; i += blockDim.x) sh_h[i] = M.h[i];
+  unsigned bad = 0;
+  if (p < npix) load_hist_row(M, hist_in + (size_t)p * M.T, hist, lane, bad);
+  __syncthreads();
+  if (bad) atomicOr(M.err, bad);
+  if (p >= npix) return;
+  const float scale = M.scale2 * kLn2;
+  for (int i = lane; i < M.D; i += 64)
+    ell_out[(size_t)p * M.D + i] = scale * cost_at(M, sh_h, hist, M.d_lo + i);
+}
+
+hipError_t launch_cost_plain(const DevModel& M, const uint16_t* hist, int npix, float* ell,
+                             hipStream_t s) {
+  const int nw = waves_for((size_t)M.T * 4, (size_t)M.W * 4);
+  if (nw == 0) return hipErrorInvalidValue;
+  const dim3 grid((npix + nw - 1) / nw);
+  hipLaunchKernelGGL(k_cost_plain, grid, dim3(64 * nw), (size_t)M.W * 4 + (size_t)nw * M.T * 4, s,
+                     M, hist, npix, ell);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- a1..a7
+template <bool kHist>
+__global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
+  extern __shared__ float smem_f[];
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* sh_h = smem_f;
+  float* sh_irf = smem_f + M.W;
+  unsigned* hist = reinterpret_cast<unsigned*>(smem_f + 2 * M.W) + (size_t)wave * (M.T + M.D);
+  float* Lb = reinterpret_cast<float*>(hist + M.T);
+  const int p = blockIdx.x * nw + wave;
+  const bool active = p < M.P;
+
+  for (int i = threadIdx.x; i < M.W; i += blockDim.x) {
+    sh_h[i] = M.h[i];
+    sh_irf[i] = M.irf[i];
+  }
+  for (int t = lane; t < M.T; t += 64) hist[t] = 0u;
+  __syncthreads();
+
+  // a1: histogram of the pixel in LDS
+  const bool faulty = active && io.faulty && io.faulty[p];
+  float K = 0.f;
+  unsigned bad = 0;
+  if (active && !faulty) {
+    if (kHist) {
+      K = load_hist_row(M, io.hist + (size_t)p * M.T, hist, lane, bad);
+    } else {
+      const int b = io.row_ptr[p], e = io.row_ptr[p + 1];
+      if (e < b) bad |= kErrRange;
+      for (int k = b + lane; k < e; k += 64) {
+        const int t = io.toa[k];
+        if ((unsigned)t < (unsigned)M.T)
+          atomicAdd(&hist[t], 1u);
+        else
+          bad |= kErrRange;
+      }
+      K = (float)(e > b ? e - b : 0);
+    }
+  }
+  if (bad) atomicOr(M.err, bad);
+  __syncthreads();
+  if (!active) return;
+
+  // a4: prior components from the previous state of the 3x3 neighbourhood
+  Comps C;
+  build_components(M, io.pm, io.pv, io.ppi, p, C);
+
+  // a3 + a5, first pass: log2 pseudo-posterior on the grid and its argmax
+  float best = -INFINITY;
+  int bi = 0x7fffffff;
+  for (int i = lane; i < M.D; i += 64) {
+    const int d = M.d_lo + i;
+    const float ell = faulty ? 0.f : cost_at(M, sh_h, hist, d);
+    const float L2 = fmaf(ell, M.scale2, log_prior2(C, (float)d));
+    Lb[i] = L2;
+    if (L2 > best) {
+      best = L2;
+      bi = i;
+    }
+  }
+  group_argmax<1, 32>(best, bi);
+
+  // a5, second pass: weights relative to the maximum, moments centred on d*
+  float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+  for (int i = lane; i < M.D; i += 64) {
+    const float w = fast_exp2(Lb[i] - best);
+    const float e = (float)(i - bi);
+    S0 += w;
+    S1 = fmaf(e, w, S1);
+    S2 = fmaf(e * e, w, S2);
+  }
+  S0 = group_sum<1, 32>(S0);
+  S1 = group_sum<1, 32>(S1);
+  S2 = group_sum<1, 32>(S2);
+  const float mu = S1 / S0;
+  const int dstar = M.d_lo + bi;
+  const float mean = (float)dstar + mu;
+  const float var = fmaxf(S2 / S0 - mu * mu, 0.f);
+
+  // a6 + a7
+  const float pi_now = faulty ? 0.5f : (io.pi_in ? io.pi_in[p] : 1.0f);
+  const bool detected = pi_now > 0.5f;
+  float r_hat = 0.f, b_hat = K / (float)M.T;
+  if (faulty) {
+    b_hat = io.pb[p];
+  } else if (detected) {
+    constexpr int U = kMaxW / 64;
+    float s[U], z[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = lane + 64 * u;
+      const int t = dstar - M.c + j;
+      const bool in = j < M.W && t >= 0 && t < M.T;
+      s[u] = in ? sh_irf[j] : 0.f;
+      z[u] = in ? (float)hist[t] : 0.f;
+    }
+    mle_reflectivity<1, 32, U>(s, z, K, (float)M.T, r_hat, b_hat);
+  }
+
+  if (lane == 0) {
+    io.nm[p] = mean;
+    io.nv[p] = var;
+    io.npi[p] = pi_now;
+    io.nb[p] = b_hat;
+    if (io.depth) io.depth[p] = detected ? mean : __builtin_nanf("");
+    if (io.var) io.var[p] = var;
+    if (io.argmax) io.argmax[p] = dstar;
+    if (io.intensity) io.intensity[p] = r_hat;
+    if (io.background) io.background[p] = b_hat;
+    if (io.pi0_next) io.pi0_next[p] = pi0_next_at(M, io.pi_in, io.faulty, p);
+  }
+}
+
+static size_t step_plain_fixed(const DevModel& M) { return (size_t)M.W * 8; }
+static size_t step_plain_per_wave(const DevModel& M) { return (size_t)(M.T + M.D) * 4; }
+
+bool plain_supported(const DevModel& M) {
+  return waves_for(step_plain_per_wave(M), step_plain_fixed(M)) > 0;
+}
+
+hipError_t launch_step_plain(const DevModel& M, const StepIO& io, bool from_hist, hipStream_t s) {
+  const int nw = waves_for(step_plain_per_wave(M), step_plain_fixed(M));
+  if (nw == 0) return hipErrorInvalidValue;
+  const dim3 grid((M.P + nw - 1) / nw);
+  const size_t lds = step_plain_fixed(M) + nw * step_plain_per_wave(M);
+  if (from_hist)
+    hipLaunchKernelGGL(k_step_plain<true>, grid, dim3(64 * nw), lds, s, M, io);
+  else
+    hipLaunchKernelGGL(k_step_plain<false>, grid, dim3(64 * nw), lds, s, M, io);
+  return hipGetLastError();
+}
+
+}  // namespace r3d

@@ -1,0 +1,255 @@
+// C ABI of libr3d: parameter validation, context management and launches.
+// Every entry point validates synchronously, then enqueues on the caller's
+// stream; nothing here synchronises except create/destroy and the explicit
+// device-status query.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "r3d_internal.hpp"
+
+struct r3d_ctx {
+  int device = 0;
+  r3d_params prm{};
+  std::vector<double> irf;
+  r3d::DevModel dm{};
+  float* d_h = nullptr;
+  float* d_irf = nullptr;
+  _Float16* d_h16 = nullptr;  // [2*W]: hi then lo
+  unsigned* d_err = nullptr;
+};
+
+namespace {
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+r3d_status check_params(const r3d_params* p) {
+  if (!p) return R3D_EINVAL;
+  if (p->rows < 1 || p->cols < 1) return R3D_EINVAL;
+  if ((int64_t)p->rows * p->cols > (int64_t)1 << 30) return R3D_EUNSUPPORTED;
+  if (p->T < 1 || p->T > 32767) return R3D_EINVAL;
+  if (p->D < 1 || p->D > 32768) return R3D_EINVAL;
+  if (p->W < 1 || p->W > r3d::kMaxW) return R3D_EINVAL;
+  if (p->c < 0 || p->c >= p->W) return R3D_EINVAL;
+  if (!p->irf) return R3D_EINVAL;
+  if (!finite_pos(p->beta) || !finite_pos(p->sigma_rw2)) return R3D_EINVAL;
+  if (!std::isfinite(p->d_min) || !std::isfinite(p->d_max) || !(p->d_max > p->d_min))
+    return R3D_EINVAL;
+  double s = 0.0;
+  for (int j = 0; j < p->W; ++j) {
+    if (!std::isfinite(p->irf[j]) || p->irf[j] < 0.0) return R3D_EINVAL;
+    s += p->irf[j];
+  }
+  if (!(s > 0.0)) return R3D_EINVAL;
+  double n = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    if (!std::isfinite(p->nu[k]) || p->nu[k] < 0.0) return R3D_EINVAL;
+    n += p->nu[k];
+  }
+  if (!(n > 0.0)) return R3D_EINVAL;
+  if (p->precision < R3D_FP32 || p->precision > R3D_FP16X2_MFMA) return R3D_EINVAL;
+  return R3D_OK;
+}
+
+r3d_status check_state(const r3d_state* s) {
+  if (!s || !s->m || !s->v || !s->pi || !s->b) return R3D_EINVAL;
+  return R3D_OK;
+}
+
+bool same_buffer(const r3d_state* a, const r3d_state* b) {
+  const float* pa[4] = {a->m, a->v, a->pi, a->b};
+  const float* pb[4] = {b->m, b->v, b->pi, b->b};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      if (pa[i] == pb[j]) return true;
+  return false;
+}
+
+r3d::StepIO make_io(const float* pi_in, const uint8_t* faulty, const r3d_state* prev,
+                    const r3d_state* next, const r3d_out* out) {
+  r3d::StepIO io{};
+  io.pi_in = pi_in;
+  io.faulty = faulty;
+  io.pm = prev->m;
+  io.pv = prev->v;
+  io.ppi = prev->pi;
+  io.pb = prev->b;
+  io.nm = next->m;
+  io.nv = next->v;
+  io.npi = next->pi;
+  io.nb = next->b;
+  if (out) {
+    io.depth = out->depth;
+    io.var = out->var;
+    io.intensity = out->intensity;
+    io.background = out->background;
+    io.pi0_next = out->pi0_next;
+    io.argmax = out->argmax;
+  }
+  return io;
+}
+
+r3d_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return R3D_OK;
+  if (e == hipErrorInvalidValue) return R3D_EUNSUPPORTED;
+  if (e == hipErrorOutOfMemory) return R3D_ENOMEM;
+  return R3D_EHIP;
+}
+
+void free_ctx(r3d_ctx* c) {
+  if (!c) return;
+  if (c->d_h) (void)hipFree(c->d_h);
+  if (c->d_irf) (void)hipFree(c->d_irf);
+  if (c->d_h16) (void)hipFree(c->d_h16);
+  if (c->d_err) (void)hipFree(c->d_err);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* r3d_status_string(r3d_status s) {
+  switch (s) {
+    case R3D_OK: return "ok";
+    case R3D_EINVAL: return "invalid argument";
+    case R3D_ERANGE: return "photon time of arrival outside [0, T)";
+    case R3D_EOVERFLOW: return "histogram count not an integer in [0, 2048]";
+    case R3D_ENOMEM: return "device allocation failed";
+    case R3D_EHIP: return "HIP runtime error";
+    case R3D_EUNSUPPORTED: return "unsupported size or option";
+  }
+  return "unknown status";
+}
+
+r3d_status r3d_create(const r3d_params* params, r3d_ctx** out) {
+  if (!out) return R3D_EINVAL;
+  *out = nullptr;
+  r3d_status st = check_params(params);
+  if (st != R3D_OK) return st;
+  r3d_ctx* c = new (std::nothrow) r3d_ctx();
+  if (!c) return R3D_ENOMEM;
+  c->prm = *params;
+  c->irf.assign(params->irf, params->irf + params->W);
+  c->prm.irf = nullptr;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    free_ctx(c);
+    return R3D_EHIP;
+  }
+  const int W = params->W;
+  double* d_irf64 = nullptr;
+  if (hipMalloc(&c->d_h, W * sizeof(float)) != hipSuccess ||
+      hipMalloc(&c->d_irf, W * sizeof(float)) != hipSuccess ||
+      hipMalloc(&c->d_h16, 2 * W * sizeof(_Float16)) != hipSuccess ||
+      hipMalloc(&c->d_err, sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&d_irf64, W * sizeof(double)) != hipSuccess) {
+    if (d_irf64) (void)hipFree(d_irf64);
+    free_ctx(c);
+    return R3D_ENOMEM;
+  }
+  hipError_t e = hipMemcpy(d_irf64, c->irf.data(), W * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(unsigned));
+  if (e == hipSuccess)
+    e = r3d::launch_prepare_irf(d_irf64, W, params->beta, c->d_h, c->d_irf, c->d_h16,
+                                c->d_h16 + W, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(d_irf64);
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return R3D_EHIP;
+  }
+
+  r3d::DevModel& m = c->dm;
+  m.rows = params->rows;
+  m.cols = params->cols;
+  m.P = params->rows * params->cols;
+  m.T = params->T;
+  m.d_lo = params->d_lo;
+  m.D = params->D;
+  m.W = W;
+  m.c = params->c;
+  m.scale2 = (float)((params->beta + 1.0) / params->beta * 1.4426950408889634);
+  m.m_flat = (float)(0.5 * (params->d_min + params->d_max));
+  const double span = params->d_max - params->d_min;
+  m.v_flat = (float)(span * span / 12.0);
+  m.sigma_rw2 = (float)params->sigma_rw2;
+  for (int k = 0; k < 9; ++k) {
+    m.nu[k] = (float)params->nu[k];
+    m.lognu2[k] = params->nu[k] > 0.0 ? (float)std::log2(params->nu[k]) : -INFINITY;
+  }
+  m.h = c->d_h;
+  m.irf = c->d_irf;
+  m.h16hi = c->d_h16;
+  m.h16lo = c->d_h16 + W;
+  m.err = c->d_err;
+  if (!r3d::plain_supported(m)) {
+    free_ctx(c);
+    return R3D_EUNSUPPORTED;
+  }
+  *out = c;
+  return R3D_OK;
+}
+
+void r3d_destroy(r3d_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  free_ctx(ctx);
+}
+
+r3d_status r3d_state_init(r3d_ctx* ctx, const r3d_state* st, void* stream) {
+  if (!ctx || check_state(st) != R3D_OK) return R3D_EINVAL;
+  return hip_status(r3d::launch_state_init(ctx->dm, st->m, st->v, st->pi, st->b,
+                                           (hipStream_t)stream));
+}
+
+r3d_status r3d_histogram(r3d_ctx* ctx, const int32_t* row_ptr, const int16_t* toa,
+                         uint16_t* hist, void* stream) {
+  if (!ctx || !row_ptr || !hist) return R3D_EINVAL;
+  return hip_status(r3d::launch_histogram(ctx->dm, row_ptr, toa, hist, (hipStream_t)stream));
+}
+
+r3d_status r3d_cost(r3d_ctx* ctx, const uint16_t* hist, int32_t npix, float* ell, void* stream) {
+  if (!ctx || !hist || !ell || npix < 0) return R3D_EINVAL;
+  if (npix == 0) return R3D_OK;
+  return hip_status(r3d::launch_cost_plain(ctx->dm, hist, npix, ell, (hipStream_t)stream));
+}
+
+r3d_status r3d_step_csr(r3d_ctx* ctx, const int32_t* row_ptr, const int16_t* toa,
+                        const float* pi_in, const uint8_t* faulty, const r3d_state* prev,
+                        const r3d_state* next, const r3d_out* out, void* stream) {
+  if (!ctx || !row_ptr) return R3D_EINVAL;
+  if (check_state(prev) != R3D_OK || check_state(next) != R3D_OK) return R3D_EINVAL;
+  if (same_buffer(prev, next)) return R3D_EINVAL;
+  if (ctx->prm.precision != R3D_FP32) return R3D_EUNSUPPORTED;
+  r3d::StepIO io = make_io(pi_in, faulty, prev, next, out);
+  io.row_ptr = row_ptr;
+  io.toa = toa;
+  return hip_status(r3d::launch_step_plain(ctx->dm, io, false, (hipStream_t)stream));
+}
+
+r3d_status r3d_step_hist(r3d_ctx* ctx, const uint16_t* hist, const float* pi_in,
+                         const uint8_t* faulty, const r3d_state* prev, const r3d_state* next,
+                         const r3d_out* out, void* stream) {
+  if (!ctx || !hist) return R3D_EINVAL;
+  if (check_state(prev) != R3D_OK || check_state(next) != R3D_OK) return R3D_EINVAL;
+  if (same_buffer(prev, next)) return R3D_EINVAL;
+  if (ctx->prm.precision != R3D_FP32) return R3D_EUNSUPPORTED;
+  r3d::StepIO io = make_io(pi_in, faulty, prev, next, out);
+  io.hist = hist;
+  return hip_status(r3d::launch_step_plain(ctx->dm, io, true, (hipStream_t)stream));
+}
+
+r3d_status r3d_last_device_status(r3d_ctx* ctx, void* stream) {
+  if (!ctx) return R3D_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return R3D_EHIP;
+  unsigned bits = 0;
+  if (hipMemcpy(&bits, ctx->d_err, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
+    return R3D_EHIP;
+  if (hipMemset(ctx->d_err, 0, sizeof(unsigned)) != hipSuccess) return R3D_EHIP;
+  if (bits & r3d::kErrRange) return R3D_ERANGE;
+  if (bits & r3d::kErrOverflow) return R3D_EOVERFLOW;
+  return R3D_OK;
+}
+
+}  // extern "C"

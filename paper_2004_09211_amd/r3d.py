@@ -1,0 +1,260 @@
+"""ctypes binding of libr3d (include/r3d.h): argument marshalling only.
+
+Every computation happens in the HIP library; this module converts torch
+tensors to device pointers and the current torch stream to a hipStream_t.
+If the library is not built, ``load()`` raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int32, c_void_p, c_char_p
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libr3d.so")
+
+R3D_FP32, R3D_FP16_MFMA, R3D_FP16X2_MFMA = 0, 1, 2
+PRECISIONS = {"fp32": R3D_FP32, "fp16": R3D_FP16_MFMA, "fp16x2": R3D_FP16X2_MFMA}
+
+STATUS = {0: "R3D_OK", -1: "R3D_EINVAL", -2: "R3D_ERANGE", -3: "R3D_EOVERFLOW",
+          -4: "R3D_ENOMEM", -5: "R3D_EHIP", -6: "R3D_EUNSUPPORTED"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("rows", c_int32), ("cols", c_int32), ("T", c_int32),
+                ("d_lo", c_int32), ("D", c_int32), ("d_min", c_double),
+                ("d_max", c_double), ("beta", c_double), ("W", c_int32),
+                ("c", c_int32), ("irf", POINTER(c_double)), ("nu", c_double * 9),
+                ("sigma_rw2", c_double), ("precision", c_int32)]
+
+
+class CState(ctypes.Structure):
+    _fields_ = [("m", c_void_p), ("v", c_void_p), ("pi", c_void_p), ("b", c_void_p)]
+
+
+class COut(ctypes.Structure):
+    _fields_ = [("depth", c_void_p), ("var", c_void_p), ("intensity", c_void_p),
+                ("background", c_void_p), ("pi0_next", c_void_p), ("argmax", c_void_p)]
+
+
+#: every symbol the header declares, with (restype, argtypes)
+SIGNATURES = {
+    "r3d_create": (c_int32, [POINTER(Params), POINTER(c_void_p)]),
+    "r3d_destroy": (None, [c_void_p]),
+    "r3d_state_init": (c_int32, [c_void_p, POINTER(CState), c_void_p]),
+    "r3d_histogram": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "r3d_cost": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "r3d_step_csr": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               POINTER(CState), POINTER(CState), POINTER(COut), c_void_p]),
+    "r3d_step_hist": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
+                                POINTER(CState), POINTER(CState), POINTER(COut), c_void_p]),
+    "r3d_last_device_status": (c_int32, [c_void_p, c_void_p]),
+    "r3d_status_string": (c_char_p, [c_int32]),
+}
+
+_lib = None
+
+
+class R3DError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = STATUS.get(status, str(status))
+        if _lib is not None:
+            msg += ": " + _lib.r3d_status_string(status).decode()
+        super().__init__(f"{what}: {msg}" if what else msg)
+
+
+def load(path: Optional[str] = None):
+    """Load libr3d.so (built in-tree by ``build.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"libr3d.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise R3DError(status, what)
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class State:
+    m: torch.Tensor
+    v: torch.Tensor
+    pi: torch.Tensor
+    b: torch.Tensor
+
+    @classmethod
+    def empty(cls, P: int, device="cuda"):
+        return cls(*(torch.empty(P, dtype=torch.float32, device=device) for _ in range(4)))
+
+    def c(self) -> CState:
+        return CState(*(_ptr(t, torch.float32) for t in (self.m, self.v, self.pi, self.b)))
+
+    def clone(self) -> "State":
+        return State(self.m.clone(), self.v.clone(), self.pi.clone(), self.b.clone())
+
+
+@dataclass
+class Outputs:
+    depth: Optional[torch.Tensor] = None
+    var: Optional[torch.Tensor] = None
+    intensity: Optional[torch.Tensor] = None
+    background: Optional[torch.Tensor] = None
+    pi0_next: Optional[torch.Tensor] = None
+    argmax: Optional[torch.Tensor] = None
+
+    @classmethod
+    def empty(cls, P: int, device="cuda"):
+        f = lambda: torch.empty(P, dtype=torch.float32, device=device)
+        return cls(f(), f(), f(), f(), f(), torch.empty(P, dtype=torch.int32, device=device))
+
+    def c(self) -> COut:
+        return COut(_ptr(self.depth, torch.float32), _ptr(self.var, torch.float32),
+                    _ptr(self.intensity, torch.float32), _ptr(self.background, torch.float32),
+                    _ptr(self.pi0_next, torch.float32), _ptr(self.argmax, torch.int32))
+
+
+def make_params(p: dict, precision=R3D_FP32):
+    """Build the C parameter struct from a parameter dict; returns the struct
+    and the host IRF array it points to (keep both alive during the call)."""
+    irf = np.ascontiguousarray(np.asarray(p["irf"], dtype=np.float64))
+    prm = Params()
+    prm.rows, prm.cols, prm.T = int(p["rows"]), int(p["cols"]), int(p["T"])
+    prm.d_lo, prm.D = int(p["d_lo"]), int(p["D"])
+    prm.d_min, prm.d_max = float(p["d_min"]), float(p["d_max"])
+    prm.beta = float(p["beta"])
+    prm.W, prm.c = int(irf.shape[0]), int(p["c"])
+    prm.irf = irf.ctypes.data_as(POINTER(c_double))
+    for k in range(9):
+        prm.nu[k] = float(p["nu"][k])
+    prm.sigma_rw2 = float(p["sigma_rw2"])
+    prm.precision = int(PRECISIONS.get(precision, precision))
+    return prm, irf
+
+
+class Context:
+    """An r3d_ctx: model parameters uploaded to the current device."""
+
+    def __init__(self, params: dict, precision=R3D_FP32):
+        lib = load()
+        prm, self._irf = make_params(params, precision)
+        h = c_void_p()
+        _check(lib.r3d_create(byref(prm), byref(h)), "r3d_create")
+        self._h = h
+        self.P = prm.rows * prm.cols
+        self.T, self.D = prm.T, prm.D
+        self.precision = prm.precision
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.r3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state_init(self, st: State, stream=None):
+        cs = st.c()
+        _check(_lib.r3d_state_init(self._h, byref(cs), _stream(stream)), "r3d_state_init")
+
+    def histogram(self, row_ptr, toa, out: Optional[torch.Tensor] = None, stream=None):
+        if out is None:
+            out = torch.empty((self.P, self.T), dtype=torch.float16, device=row_ptr.device)
+        _check(_lib.r3d_histogram(self._h, _ptr(row_ptr, torch.int32), _ptr(toa, torch.int16),
+                                  _ptr(out, torch.float16), _stream(stream)), "r3d_histogram")
+        return out
+
+    def cost(self, hist: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        npix = hist.shape[0]
+        if out is None:
+            out = torch.empty((npix, self.D), dtype=torch.float32, device=hist.device)
+        _check(_lib.r3d_cost(self._h, _ptr(hist, torch.float16), npix, _ptr(out, torch.float32),
+                             _stream(stream)), "r3d_cost")
+        return out
+
+    def step_csr(self, row_ptr, toa, prev: State, nxt: State, out: Outputs,
+                 pi_in=None, faulty=None, stream=None):
+        cp, cn, co = prev.c(), nxt.c(), out.c()
+        _check(_lib.r3d_step_csr(self._h, _ptr(row_ptr, torch.int32), _ptr(toa, torch.int16),
+                                 _ptr(pi_in, torch.float32), _ptr(faulty, torch.uint8),
+                                 byref(cp), byref(cn), byref(co), _stream(stream)), "r3d_step_csr")
+
+    def step_hist(self, hist, prev: State, nxt: State, out: Outputs, pi_in=None, faulty=None,
+                  stream=None):
+        cp, cn, co = prev.c(), nxt.c(), out.c()
+        _check(_lib.r3d_step_hist(self._h, _ptr(hist, torch.float16),
+                                  _ptr(pi_in, torch.float32), _ptr(faulty, torch.uint8),
+                                  byref(cp), byref(cn), byref(co), _stream(stream)), "r3d_step_hist")
+
+    def last_device_status(self, stream=None) -> int:
+        return int(_lib.r3d_last_device_status(self._h, _stream(stream)))
+
+
+class R3DFilter:
+    """Online filter over frames (Algorithm 1) on one device: owns the two
+    ping-pong states; ``step`` returns the frame's outputs."""
+
+    def __init__(self, params: dict, precision=R3D_FP32, device="cuda"):
+        self.ctx = Context(params, precision)
+        self.P = self.ctx.P
+        self.device = device
+        self.prev = State.empty(self.P, device)
+        self.next = State.empty(self.P, device)
+        self.ctx.state_init(self.prev)
+
+    @property
+    def state(self) -> State:
+        return self.prev
+
+    def set_state(self, st: State):
+        for a, b in zip((self.prev.m, self.prev.v, self.prev.pi, self.prev.b),
+                        (st.m, st.v, st.pi, st.b)):
+            a.copy_(b)
+
+    def step(self, frame, pi_in=None, faulty=None, out: Optional[Outputs] = None) -> Outputs:
+        """``frame`` is a (row_ptr, toa) pair of device tensors or an fp16
+        histogram [P, T]."""
+        out = Outputs.empty(self.P, self.device) if out is None else out
+        if isinstance(frame, torch.Tensor):
+            self.ctx.step_hist(frame, self.prev, self.next, out, pi_in, faulty)
+        else:
+            row_ptr, toa = frame
+            self.ctx.step_csr(row_ptr, toa, self.prev, self.next, out, pi_in, faulty)
+        self.prev, self.next = self.next, self.prev
+        return out
