@@ -1,0 +1,186 @@
+#!/usr/bin/env python
+"""Throughput of the R3DSP hot path on one MI355X.
+
+Workload (the metric's configuration): 256x256 pixels x 30 frames, T = 4096
+timing bins, fp16 photon-count histograms (signal Poisson(50) spread by a
+sigma = 6 bin IRF with 64 taps, background Poisson(400) uniform), beta = 0.5,
+3x3 spatio-temporal fusion. One step = one pass of the whole per-frame path
+(a1..a7: cost, prior, argmax/moments, state update, background/reflectivity,
+prior presence) over the 30 frames, starting from the initial state. Inputs
+are drawn on the device before timing (15 GiB resident in HBM).
+
+Prints one JSON line with the matrix-core form's pixel-frames/s, the plain
+fp32 form's rate on the same workload, the roofline of the step kernel
+(HBM-bound: algorithmic bytes per launch over the launch time measured with
+events on the launch stream) and the FP64 CPU oracle's rate on a bounded
+sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pixel-frames/sec (cost+argmax+fusion) at 256×256×4096 bins; MFMA/batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_pixel_frame(T: int) -> int:
+    """fp16 histogram row + previous state (m, v, pi, b) + next state +
+    six per-pixel outputs, each read or written once."""
+    return 2 * T + 16 + 16 + 24
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_tile_fp16x2_hist256x256x4096.json")
+KERNEL_SRCS = ["paper_2004_09211_amd/csrc/k_tile.hip", "paper_2004_09211_amd/csrc/r3d_device.hpp",
+               "paper_2004_09211_amd/csrc/r3d_tile.hpp"]
+
+
+def measured_traffic(precision: str, frames: int):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    record, if it was taken on the kernel sources as they are now (else None)."""
+    import hashlib
+    if precision != "fp16x2" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in KERNEL_SRCS))
+    if sha.hexdigest()[:16] != rec["kernel_src_sha"]:
+        return None
+    return (rec["first_frame_bytes"] + (frames - 1) * rec["steady_frame_bytes"]) / frames
+
+
+def run_gpu(args):
+    import torch
+    import synth
+    from paper_2004_09211_amd import r3d
+
+    if not os.path.exists(r3d.LIB_PATH):
+        from paper_2004_09211_amd import build
+        build.build()
+    r3d.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = synth.config4(seed=0, device=dev, frames=args.frames)
+    torch.cuda.synchronize()
+    P, F, T = wl.P, wl.nframes, wl.T
+    params = wl.params()
+
+    def make(precision):
+        ctx = r3d.Context(params, precision)
+        st = [r3d.State.empty(P, dev), r3d.State.empty(P, dev)]
+        out = r3d.Outputs.empty(P, dev)
+        return ctx, st, out
+
+    def sequence(ctx, st, out, ev=None):
+        ctx.state_init(st[0])
+        for n in range(F):
+            if ev is not None:
+                ev[0][n].record()
+            ctx.step_hist(wl.hist[n], st[n % 2], st[(n + 1) % 2], out)
+            if ev is not None:
+                ev[1][n].record()
+
+    def timed(precision, steps, warmup):
+        ctx, st, out = make(precision)
+        for _ in range(warmup):
+            sequence(ctx, st, out)
+        torch.cuda.synchronize()
+        evs = [([torch.cuda.Event(enable_timing=True) for _ in range(F)],
+                [torch.cuda.Event(enable_timing=True) for _ in range(F)]) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            sequence(ctx, st, out, evs[s])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        status = ctx.last_device_status()
+        if status != 0:
+            raise RuntimeError(f"device status {status}")
+        launch_ms = [evs[s][0][n].elapsed_time(evs[s][1][n]) for s in range(steps) for n in range(F)]
+        return wall, sum(launch_ms) / len(launch_ms)
+
+    prec = r3d.PRECISIONS[args.precision]
+    wall, launch_ms = timed(prec, args.steps, args.warmup)
+    ms_per_step = 1e3 * wall / args.steps
+    value = P * F * args.steps / wall
+    plain = None
+    if args.plain_steps > 0 and prec != r3d.R3D_FP32:
+        pw, pl = timed(r3d.R3D_FP32, args.plain_steps, 1)
+        plain = dict(value=P * F * args.plain_steps / pw, ms_per_step=1e3 * pw / args.plain_steps,
+                     launch_ms=pl, precision="fp32")
+    bytes_launch = algorithmic_bytes_per_pixel_frame(T) * P
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=measured_traffic(args.precision, F),
+                kernel="r3d step (one launch per frame)", launch_ms=round(launch_ms, 5),
+                bytes_per_launch=bytes_launch)
+    sample_hist = None
+    if not args.no_cpu_baseline:
+        r = args.cpu_rows
+        sample_hist = [wl.hist[n].reshape(wl.rows, wl.cols, T)[:r, :r].reshape(r * r, T)
+                       .float().cpu().numpy() for n in range(args.cpu_frames)]
+    res = dict(value=value, ms_per_step=ms_per_step, plain=plain, roofline=roof, P=P, F=F, T=T,
+               params=params)
+    return res, sample_hist
+
+
+def cpu_baseline(params, sample_hist, rows):
+    import numpy as np
+    import oracle
+    p = dict(params)
+    p["rows"] = p["cols"] = rows
+    model = oracle.Model.from_params(p)
+    frames = [h.astype(np.int64) for h in sample_hist]
+    t0 = time.perf_counter()
+    oracle.run(model, frames)
+    dt = time.perf_counter() - t0
+    n = rows * rows * len(frames)
+    return dict(value=round(n / dt, 2), unit="pixel-frames/s", cores=1, kind="oracle",
+                sample=f"{rows}x{rows} crop x {len(frames)} frames of the same workload "
+                       f"({n} pixel-frames, {dt:.1f} s, single thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp16x2", choices=["fp32", "fp16", "fp16x2"])
+    ap.add_argument("--frames", type=int, default=30)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=20)
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the hot path is measured on a single MI355X "
+              "(multi-GPU sharding is a design note, not implemented); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    res, sample = run_gpu(args)
+    cpu = cpu_baseline(res["params"], sample, args.cpu_rows) if sample is not None else None
+    line = dict(
+        metric=METRIC, value=round(res["value"], 1), unit="pixel-frames/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=round(res["ms_per_step"], 4),
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype={"fp32": "f32", "fp16": "fp16 mfma, f32 acc", "fp16x2": "fp16x2 mfma, f32 acc"}[args.precision],
+        data="synthetic",
+        config=dict(workload=f"hist {res['P'] // 256}x256 x {res['F']} frames, T={res['T']}, fp16 "
+                             f"histograms, W=64, beta=0.5, 3x3 fusion",
+                    pixels=res["P"], frames=res["F"], T=res["T"], precision=args.precision,
+                    parallelism="single GPU"),
+        plain_fp32=(None if res["plain"] is None else
+                    dict(value=round(res["plain"]["value"], 1),
+                         ms_per_step=round(res["plain"]["ms_per_step"], 3),
+                         speedup=round(res["value"] / res["plain"]["value"], 3))),
+        roofline=res["roofline"], cpu_baseline=cpu)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

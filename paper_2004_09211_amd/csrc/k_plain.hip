@@ -212,6 +212,7 @@ __global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
   // a4: prior components from the previous state of the 3x3 neighbourhood
   Comps C;
   build_components(M, io.pm, io.pv, io.ppi, p, C);
+  const unsigned cmask = __builtin_amdgcn_readfirstlane(C.live);  // one pixel per wavefront
 
   // a3 + a5, first pass: log2 pseudo-posterior on the grid and its argmax
   float best = -INFINITY;
@@ -219,7 +220,7 @@ __global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
   for (int i = lane; i < M.D; i += 64) {
     const int d = M.d_lo + i;
     const float ell = faulty ? 0.f : cost_at(M, sh_h, hist, d);
-    const float L2 = fmaf(ell, M.scale2, log_prior2(C, (float)d));
+    const float L2 = fmaf(ell, M.scale2, log_prior2(C, (float)d, cmask));
     Lb[i] = L2;
     if (L2 > best) {
       best = L2;
@@ -254,6 +255,7 @@ __global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
   } else if (detected) {
     constexpr int U = kMaxW / 64;
     float s[U], z[U];
+    float S = 0.f, Kw = 0.f, nw = 0.f;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = lane + 64 * u;
@@ -261,8 +263,24 @@ __global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
       const bool in = j < M.W && t >= 0 && t < M.T;
       s[u] = in ? sh_irf[j] : 0.f;
       z[u] = in ? (float)hist[t] : 0.f;
+      S += s[u];
+      Kw += z[u];
+      nw += in ? 1.f : 0.f;
     }
-    mle_reflectivity<1, 32, U>(s, z, K, (float)M.T, r_hat, b_hat);
+    S = group_sum<1, 32>(S);
+    Kw = group_sum<1, 32>(Kw);
+    nw = group_sum<1, 32>(nw);
+    auto terms = [&](float r, float b, float SoT, float& g1, float& g2) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (z[u] > 0.f) {
+          const float q = (s[u] - SoT) * fast_rcp(fmaf(r, s[u], b));
+          g1 = fmaf(z[u], q, g1);
+          g2 = fmaf(-z[u] * q, q, g2);
+        }
+      }
+    };
+    mle_reflectivity<1, 32>(terms, K, S, Kw, nw, (float)M.T, r_hat, b_hat);
   }
 
   if (lane == 0) {

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "r3d_internal.hpp"
+#include "r3d_tile.hpp"
 
 struct r3d_ctx {
   int device = 0;
@@ -212,7 +213,10 @@ r3d_status r3d_histogram(r3d_ctx* ctx, const int32_t* row_ptr, const int16_t* to
 r3d_status r3d_cost(r3d_ctx* ctx, const uint16_t* hist, int32_t npix, float* ell, void* stream) {
   if (!ctx || !hist || !ell || npix < 0) return R3D_EINVAL;
   if (npix == 0) return R3D_OK;
-  return hip_status(r3d::launch_cost_plain(ctx->dm, hist, npix, ell, (hipStream_t)stream));
+  if (ctx->prm.precision == R3D_FP32)
+    return hip_status(r3d::launch_cost_plain(ctx->dm, hist, npix, ell, (hipStream_t)stream));
+  return hip_status(r3d::launch_cost_tile(ctx->dm, ctx->prm.precision, hist, npix, ell,
+                                          (hipStream_t)stream));
 }
 
 r3d_status r3d_step_csr(r3d_ctx* ctx, const int32_t* row_ptr, const int16_t* toa,
@@ -234,9 +238,12 @@ r3d_status r3d_step_hist(r3d_ctx* ctx, const uint16_t* hist, const float* pi_in,
   if (!ctx || !hist) return R3D_EINVAL;
   if (check_state(prev) != R3D_OK || check_state(next) != R3D_OK) return R3D_EINVAL;
   if (same_buffer(prev, next)) return R3D_EINVAL;
-  if (ctx->prm.precision != R3D_FP32) return R3D_EUNSUPPORTED;
   r3d::StepIO io = make_io(pi_in, faulty, prev, next, out);
   io.hist = hist;
+  const int engine = ctx->prm.precision;  // r3d_precision values are the engine ids
+  if (r3d::tile_supported(ctx->dm, engine) && ((uintptr_t)hist & 15u) == 0)
+    return hip_status(r3d::launch_step_tile(ctx->dm, engine, io, (hipStream_t)stream));
+  if (engine != R3D_FP32) return R3D_EUNSUPPORTED;
   return hip_status(r3d::launch_step_plain(ctx->dm, io, true, (hipStream_t)stream));
 }
 

@@ -12,6 +12,7 @@ namespace r3d {
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ float half_bits_to_float(uint16_t b) {
   _Float16 h;
@@ -60,9 +61,33 @@ __device__ __forceinline__ void group_argmax(float& v, int& i) {
 // walk adds sigma_rw2 to its variance. Stored as the log2-density
 //   q_k(d) = w2[k] - (d - m[k])^2 * k2[k],
 //   w2 = log2(nu_k) - log2(2 pi V)/2,  k2 = log2(e) / (2 V).
+// Components with identical (m, V) (all flat ones, for instance) are merged
+// into the first of them by adding their weights; a merged or zero-weight
+// slot has w2 = -inf and its bit cleared in ``live``.
 struct Comps {
   float m[9], k2[9], w2[9];
+  unsigned live;
 };
+
+__device__ __forceinline__ float log2_add(float a, float b) {
+  const float mx = fmaxf(a, b), mn = fminf(a, b);
+  return mx + log2f(1.0f + exp2f(mn - mx));
+}
+
+// merge components with identical (m, V) into the first of them
+__device__ __forceinline__ void merge_components(Comps& C) {
+#pragma unroll
+  for (int k = 1; k < 9; ++k)
+#pragma unroll
+    for (int j = 0; j < k; ++j)
+      if (C.w2[j] > -INFINITY && C.w2[k] > -INFINITY && C.m[j] == C.m[k] && C.k2[j] == C.k2[k]) {
+        C.w2[j] = log2_add(C.w2[j], C.w2[k]);
+        C.w2[k] = -INFINITY;
+      }
+  C.live = 0u;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) C.live |= (C.w2[k] > -INFINITY ? 1u : 0u) << k;
+}
 
 __device__ __forceinline__ void build_components(const DevModel& M, const float* __restrict__ pm,
                                                  const float* __restrict__ pv,
@@ -85,21 +110,28 @@ __device__ __forceinline__ void build_components(const DevModel& M, const float*
     C.k2[k] = 0.5f * kLog2e / V;
     C.w2[k] = M.lognu2[k] - 0.5f * (kLog2TwoPi + log2f(V));
   }
+  merge_components(C);
 }
 
-// log2 f(d) by a max-shifted log-sum-exp over the 9 components.
-__device__ __forceinline__ float log_prior2(const Comps& C, float d) {
+// log2 f(d) by a max-shifted log-sum-exp over the components whose bit is set
+// in ``mask`` (wave-uniform, so skipped components cost nothing). Returns
+// -inf when none of this lane's components is in the mask.
+__device__ __forceinline__ float log_prior2(const Comps& C, float d, unsigned mask) {
   float q[9];
   float mx = -INFINITY;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const float e = d - C.m[k];
-    q[k] = C.w2[k] - e * e * C.k2[k];
-    mx = fmaxf(mx, q[k]);
+    if (mask & (1u << k)) {
+      const float e = d - C.m[k];
+      q[k] = C.w2[k] - e * e * C.k2[k];
+      mx = fmaxf(mx, q[k]);
+    }
   }
+  if (mx == -INFINITY) return -INFINITY;
   float s = 0.f;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) s += fast_exp2(q[k] - mx);
+  for (int k = 0; k < 9; ++k)
+    if (mask & (1u << k)) s += fast_exp2(q[k] - mx);
   return mx + fast_log2(s);
 }
 
@@ -137,53 +169,66 @@ __device__ __forceinline__ float pi0_next_at(const DevModel& M, const float* __r
 // b(r) = (K - r S)/T with r in [0, K/S]; the likelihood restricted to that
 // segment is concave and its derivative
 //   phi'(r) = sum_{t in window} z_t (s_t - S/T) / (r s_t + b) - K_out (S/T) / b
-// (K_out = photons outside the IRF window, where s_t = 0) is bisected.
-// Each lane of the group holds U window taps (s = 0, z = 0 for unused slots).
-template <int kLo, int kHi, int U>
-__device__ __forceinline__ void mle_reflectivity(const float (&s)[U], const float (&z)[U], float K,
+// (K_out = photons outside the IRF window, where s_t = 0) is decreasing.
+// Its root is found by Newton steps on phi' kept inside a shrinking bracket
+// (bisection when a step leaves it). ``terms(r, b, SoT, g1, g2)`` adds this
+// lane's window taps to phi' (g1) and phi'' (g2); the group sums them.
+template <int kLo, int kHi, class Terms>
+__device__ __forceinline__ void mle_reflectivity(Terms terms, float K, float S, float Kw, float nwin,
                                                  float T, float& r_hat, float& b_hat) {
-  float S = 0.f, Kw = 0.f;
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    S += s[u];
-    Kw += z[u];
-  }
-  S = group_sum<kLo, kHi>(S);
-  Kw = group_sum<kLo, kHi>(Kw);
   const float invT = 1.0f / T;
   r_hat = 0.f;
   b_hat = K * invT;
   if (!(K > 0.f) || !(S > 0.f)) return;
   const float SoT = S * invT;
   const float Kout = K - Kw;
-  auto dphi = [&](float r) {
+  auto eval = [&](float r, float& g1, float& g2) {
     const float b = fmaxf((K - r * S) * invT, 0.f);
-    float acc = 0.f;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (z[u] > 0.f) acc += z[u] * (s[u] - SoT) / (r * s[u] + b);
-    acc = group_sum<kLo, kHi>(acc);
-    if (Kout > 0.f) acc -= Kout * SoT / b;
-    return acc;
+    float a1 = 0.f, a2 = 0.f;
+    terms(r, b, SoT, a1, a2);
+    g1 = group_sum<kLo, kHi>(a1);
+    g2 = group_sum<kLo, kHi>(a2);
+    if (Kout > 0.f) {
+      const float q = SoT / b;
+      g1 -= Kout * q;
+      g2 -= Kout * q * q;
+    }
   };
-  if (!(dphi(0.f) > 0.f)) return;
-  float hi = K / S;
-  if (dphi(hi) >= 0.f) {
+  float g1, g2;
+  eval(0.f, g1, g2);
+  if (!(g1 > 0.f)) return;
+  float lo = 0.f, hi = K / S;
+  eval(hi, g1, g2);
+  if (g1 >= 0.f) {
     r_hat = hi;
     b_hat = 0.f;
     return;
   }
-  float lo = 0.f;
-  for (int it = 0; it < 64; ++it) {
-    const float mid = 0.5f * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (dphi(mid) > 0.f)
-      lo = mid;
+  // start from the window excess over the background it would hold
+  float r = (Kw - K * nwin * invT) / fmaxf(S - nwin * SoT, 1e-30f);
+  if (!(r > lo && r < hi)) r = 0.5f * (lo + hi);
+  // fp32 sums of the score carry rounding noise near the root, so the
+  // iteration stops at a step (or bracket width) of 1e-5 * max(r, 1)
+  for (int it = 0; it < 16; ++it) {
+    eval(r, g1, g2);
+    if (g1 > 0.f)
+      lo = r;
     else
-      hi = mid;
+      hi = r;
+    if (g1 == 0.f) break;
+    const float step = g1 / g2;
+    const float tol = 1e-5f * fmaxf(r, 1.0f);
+    if (fabsf(step) <= tol) {  // converged: the Newton step is below the noise floor
+      r = fminf(fmaxf(r - step, lo), hi);
+      break;
+    }
+    float rn = r - step;
+    if (!(rn > lo && rn < hi)) rn = 0.5f * (lo + hi);  // outside the bracket: bisect
+    r = rn;
+    if (!(hi - lo > tol)) break;
   }
-  r_hat = 0.5f * (lo + hi);
-  b_hat = fmaxf((K - r_hat * S) * invT, 0.f);
+  r_hat = r;
+  b_hat = fmaxf((K - r * S) * invT, 0.f);
 }
 
 }  // namespace r3d

@@ -22,9 +22,10 @@ import oracle
 def frame_hist(frame, T, pixels=None):
     """Oracle-side histogram of a frame (CSR pair or fp16 [P, T] tensor)."""
     if isinstance(frame, torch.Tensor):
-        h = frame.float().cpu().numpy()
-        h = h if pixels is None else h[np.asarray(pixels)]
-        return h.astype(np.int64)
+        if pixels is not None:
+            idx = torch.as_tensor(np.asarray(pixels), dtype=torch.int64, device=frame.device)
+            frame = frame.index_select(0, idx)
+        return frame.float().cpu().numpy().astype(np.int64)
     if hasattr(frame, "row_ptr"):
         rp, toa = frame.row_ptr, frame.toa
     else:

@@ -1,0 +1,179 @@
+"""GPU parity of the tile kernels on fp16 histograms (one wavefront per 4x4
+pixel block; fp32 vector engine, fp16 and split-fp16 matrix-core engines)
+against the FP64 oracle, through the C ABI.
+
+Tolerances: fp32 and split fp16 (about 22 significant bits of irf^beta):
+argmax identical where the oracle margin exceeds 1e-3 nats, mean within
+1e-4 * max(1, sd) bins, variance 1e-3 relative. Single fp16 irf^beta has a
+relative error up to 2^-12 per tap, so its cost error is bounded by
+2^-12 * ell(d): means are held to 0.5 bin (the stated bound for this form)
+and argmax to the tie set at margin 2^-11 * max ell + 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity_util import compare, frame_hist, gpu_outputs_np, light_cone_oracle
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+ENGINES = ["fp32", "fp16", "fp16x2"]
+
+
+def hist_workload(rows=12, cols=20, frames=3, T=4096, **kw):
+    return synth.config4(frames=frames, rows=rows, cols=cols, T=T, **kw)
+
+
+def tol_for(prec):
+    if prec == "fp16":
+        return dict(mean_rel=0.5, var_rel=0.05, int_rel=0.05, margin=0.3)
+    return dict(mean_rel=1e-4, var_rel=1e-3, int_rel=1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp16x2"])
+@pytest.mark.parametrize("shape", ["c4crop", "tiny_offset"])
+def test_cost_tile_matches_oracle(lib, prec, shape):
+    if shape == "c4crop":
+        wl = hist_workload(rows=5, cols=8, frames=1)  # 40 pixels: ragged last block
+        hist = wl.hist[0].to(DEV).contiguous()
+    else:
+        wl = synth.tiny_workload(rows=3, cols=7, T=200, W=9, c=4, frames=1)
+        wl.d_lo, wl.D, wl.d_min, wl.d_max = 13, 150, 13.0, 162.0
+        ctx0 = lib.Context(wl.params())
+        hist = ctx0.histogram(wl.frames[0].row_ptr.to(DEV), wl.frames[0].toa.to(DEV))
+    ctx = lib.Context(wl.params(), prec)
+    ell = ctx.cost(hist).cpu().numpy()
+    assert ctx.last_device_status() == 0
+    ref = oracle.cost_from_histogram(frame_hist(hist, wl.T), oracle.Model.from_params(wl.params()))
+    rel = 2.5e-4 if prec == "fp16" else 2e-6
+    np.testing.assert_allclose(ell, ref, rtol=rel, atol=rel * max(1.0, ref.max()))
+
+
+@pytest.mark.parametrize("prec", ENGINES)
+def test_step_tile_teacher_forced(lib, prec):
+    """Each frame starts from the oracle's state (cast to fp32): 12x20 crop of
+    the 4096-bin histogram workload, 3 frames."""
+    wl = hist_workload()
+    model = oracle.Model.from_params(wl.params())
+    ctx = lib.Context(wl.params(), prec)
+    st = oracle.init_state(model)
+    for n in range(wl.nframes):
+        z = frame_hist(wl.hist[n], wl.T)
+        new, ref = oracle.step(model, st, z)
+        prev = lib.State(*(torch.tensor(a, dtype=torch.float32, device=DEV)
+                           for a in (st.m, st.v, st.pi, st.b)))
+        nxt = lib.State.empty(wl.P, DEV)
+        out = lib.Outputs.empty(wl.P, DEV)
+        ctx.step_hist(wl.hist[n].to(DEV).contiguous(), prev, nxt, out)
+        g = gpu_outputs_np(out)
+        g["mean"] = nxt.m.cpu().numpy()
+        rep = compare(g, ref, model=model, state=st, z=z, pixels=np.arange(wl.P),
+                      label=f"{prec} frame {n}", **tol_for(prec))
+        print(prec, n, rep)
+        st = new
+    assert ctx.last_device_status() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16x2"])
+def test_step_tile_free_running(lib, prec):
+    wl = hist_workload(rows=9, cols=11, frames=5)
+    model = oracle.Model.from_params(wl.params())
+    filt = lib.R3DFilter(wl.params(), prec, device=DEV)
+    st = oracle.init_state(model)
+    for n in range(wl.nframes):
+        o = filt.step(wl.hist[n].to(DEV).contiguous())
+        g = gpu_outputs_np(o)
+        g["mean"] = filt.state.m.cpu().numpy()
+        st, ref = oracle.step(model, st, frame_hist(wl.hist[n], wl.T))
+        rep = compare(g, ref, mean_rel=1e-3, var_rel=1e-2, int_rel=1e-2, label=f"{prec} free {n}")
+        print(prec, n, rep)
+
+
+@pytest.mark.parametrize("case", ["ragged_T_offset", "small_W", "wide_W", "faulty_pi"])
+@pytest.mark.parametrize("prec", ENGINES)
+def test_step_tile_edge_cases(lib, prec, case):
+    if case == "ragged_T_offset":
+        wl = synth.tiny_workload(rows=7, cols=6, T=200, W=13, c=6, frames=2, n_sig=15)
+        wl.d_lo, wl.D, wl.d_min, wl.d_max = 21, 150, 21.0, 170.0
+    elif case == "small_W":
+        wl = synth.tiny_workload(rows=5, cols=5, T=96, W=3, c=1, frames=2, sigma=0.7)
+    elif case == "wide_W":
+        wl = synth.tiny_workload(rows=4, cols=5, T=512, W=96, c=48, frames=2, sigma=12.0,
+                                 n_sig=60, n_bg=30)
+    else:
+        wl = synth.tiny_workload(rows=6, cols=7, T=128, W=15, c=7, frames=3, n_sig=12)
+    ctx0 = lib.Context(wl.params())
+    hists = [ctx0.histogram(f.row_ptr.to(DEV), f.toa.to(DEV)) for f in wl.frames]
+    pi_in = faulty = None
+    if case == "faulty_pi":
+        g0 = torch.Generator().manual_seed(3)
+        pi_in = [torch.rand(wl.P, generator=g0).to(DEV) for _ in hists]
+        faulty = (torch.rand(wl.P, generator=g0) < 0.15).to(torch.uint8).to(DEV)
+    model = oracle.Model.from_params(wl.params())
+    filt = lib.R3DFilter(wl.params(), prec, device=DEV)
+    st = oracle.init_state(model)
+    for n, h in enumerate(hists):
+        o = filt.step(h, pi_in=None if pi_in is None else pi_in[n], faulty=faulty)
+        g = gpu_outputs_np(o)
+        g["mean"] = filt.state.m.cpu().numpy()
+        st, ref = oracle.step(model, st, frame_hist(h, wl.T),
+                              pi_in=None if pi_in is None else pi_in[n].cpu().numpy(),
+                              faulty=None if faulty is None else faulty.cpu().numpy().astype(bool))
+        t = tol_for(prec) if prec == "fp16" else dict(mean_rel=1e-3, var_rel=1e-2, int_rel=1e-2)
+        compare(g, ref, label=f"{prec} {case} {n}", **t)
+    assert filt.ctx.last_device_status() == 0
+
+
+def test_tile_count_validation(lib):
+    wl = hist_workload(rows=4, cols=4, frames=1, T=256)
+    h = wl.hist[0].to(DEV).clone()
+    for bad in (2050.0, -1.0):
+        h2 = h.clone()
+        h2[5, 17] = bad
+        for prec in ENGINES:
+            f = lib.R3DFilter(wl.params(), prec, device=DEV)
+            f.step(h2)
+            assert f.ctx.last_device_status() == -3, (prec, bad)
+    f = lib.R3DFilter(wl.params(), "fp16x2", device=DEV)
+    f.step(h)
+    assert f.ctx.last_device_status() == 0
+
+
+@pytest.mark.parametrize("prec", ENGINES)
+def test_tile_determinism(lib, prec):
+    wl = hist_workload(rows=8, cols=8, frames=3)
+    outs = []
+    for _ in range(2):
+        f = lib.R3DFilter(wl.params(), prec, device=DEV)
+        res = []
+        for n in range(wl.nframes):
+            o = f.step(wl.hist[n].to(DEV).contiguous())
+            res.append({k: v.copy() for k, v in gpu_outputs_np(o).items()})
+        outs.append(res)
+    for a, b in zip(*outs):
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("prec", ["fp16x2", "fp32"])
+def test_full_size_sampled(lib, prec):
+    """The benchmark's configuration (256x256, T=4096, fp16 histograms) for 4
+    frames on the GPU; sampled pixels checked against the oracle's light cone
+    (edges, corners, object boundaries, random interior)."""
+    wl = synth.config4(device=DEV, frames=4)
+    filt = lib.R3DFilter(wl.params(), prec, device=DEV)
+    for n in range(wl.nframes):
+        o = filt.step(wl.hist[n])
+    g = gpu_outputs_np(o)
+    g["mean"] = filt.state.m.cpu().numpy()
+    assert filt.ctx.last_device_status() == 0
+    model = oracle.Model.from_params(wl.params())
+    rng = np.random.default_rng(1)
+    targets = np.unique(np.concatenate([rng.choice(wl.P, 5, replace=False),
+                                        [0, 255, wl.P - 1, 40 * 256 + 20, 40 * 256 + 19,
+                                         180 * 256 + 168, 100 * 256 + 100]]))
+    frames = [wl.hist[n] for n in range(wl.nframes)]
+    ref = light_cone_oracle(model, frames, targets, wl.nframes - 1)
+    sub = {k: v[targets] for k, v in g.items()}
+    compare(sub, ref, mean_rel=1e-3, var_rel=1e-2, int_rel=1e-2, label=f"{prec} full-size")
