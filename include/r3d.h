@@ -54,7 +54,8 @@ typedef enum {
     R3D_EOVERFLOW = -3,     /* an fp16 count > 2048 or < 0 (device-detected)    */
     R3D_ENOMEM = -4,        /* device allocation failed                         */
     R3D_EHIP = -5,          /* a HIP runtime call failed                        */
-    R3D_EUNSUPPORTED = -6   /* size or option outside what the kernels support  */
+    R3D_EUNSUPPORTED = -6,  /* size or option outside what the kernels support  */
+    R3D_ETIMEDOUT = -7      /* a batched item waited past its spin limit        */
 } r3d_status;
 
 /* How the cost correlation (a3) is evaluated.
@@ -151,6 +152,54 @@ r3d_status r3d_step_hist(r3d_ctx *ctx, const uint16_t *hist,
 /* Synchronise the stream, then read and clear the device error word:
  * R3D_OK, R3D_ERANGE or R3D_EOVERFLOW (the first kind recorded). */
 r3d_status r3d_last_device_status(r3d_ctx *ctx, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched sequences in one persistent launch.
+ *
+ * Many independent sequences of photon-list frames (each with its own
+ * context: resolution, bins, IRF, beta, ...) are run through Algorithm 1 by
+ * one persistent kernel. Work items are (frame, sequence, band of image
+ * rows); an item of frame n starts once frame n-1 of its band and of the two
+ * neighbouring bands is done (the 3x3 prior of Sec. III-A reads one halo row),
+ * so frames of different sequences and bands overlap freely. The launch
+ * (a small counter reset plus the persistent kernel) is captured once into a
+ * HIP graph at creation and replayed by r3d_batch_launch.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    r3d_ctx *ctx;                  /* model of this sequence (precision R3D_FP32)        */
+    int32_t nframes;               /* >= 1                                               */
+    const int32_t *const *row_ptr; /* HOST array of nframes DEVICE pointers, int32[P+1]  */
+    const int16_t *const *toa;     /* HOST array of nframes DEVICE pointers              */
+    r3d_state state[2];            /* device; frame n reads state[n % 2] and writes
+                                      state[(n+1) % 2]; state[0] must hold the initial
+                                      state when the batch is launched                    */
+    r3d_out out;                   /* device arrays of nframes*P elements, frame-major;
+                                      any pointer may be NULL                             */
+    const float *pi_in;            /* device [nframes*P] presence probabilities or NULL  */
+    const uint8_t *faulty;         /* device [P] mask or NULL                            */
+    int32_t chunk_rows;            /* image rows per work item, 0 = library default      */
+} r3d_sequence;
+
+typedef struct r3d_batch r3d_batch;
+
+/* Validate the sequences, upload their descriptors (the pointers are kept:
+ * the caller's buffers must stay allocated while the batch exists), size the
+ * work queue and capture the launch into a graph. spin_limit bounds the
+ * dependency polls of one item (0 = a default far above any legitimate
+ * wait); an exhausted limit records R3D_ETIMEDOUT and the item proceeds.
+ * Synchronous. Histogram lengths up to 7936 bins. */
+r3d_status r3d_batch_create(const r3d_sequence *seqs, int32_t nseq, uint32_t spin_limit,
+                            r3d_batch **out);
+
+/* Replay the captured launch on the stream (asynchronous). */
+r3d_status r3d_batch_launch(r3d_batch *batch, void *stream);
+
+/* Synchronise the stream, then read and clear the batch's device error word
+ * (R3D_OK, R3D_ETIMEDOUT, R3D_ERANGE or R3D_EOVERFLOW). */
+r3d_status r3d_batch_status(r3d_batch *batch, void *stream);
+
+/* Destroy a batch (synchronises the device first). NULL is ignored. */
+void r3d_batch_destroy(r3d_batch *batch);
 
 /* Static description of a status code. */
 const char *r3d_status_string(r3d_status status);

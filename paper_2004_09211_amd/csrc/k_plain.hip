@@ -2,11 +2,11 @@
 // histogramming (a1), the cost alone (a3) and the fused per-frame step
 // (a1..a7) with one wavefront per pixel.
 //
-// The fused step keeps the pixel's histogram and its log pseudo-posterior on
-// the depth grid in LDS: lanes own depth bins d = d_lo + lane + 64 i, the cost
-// correlation reads the histogram window from LDS, the argmax and the
-// moments are wavefront reductions, and lane 0 writes the pixel's outputs.
+// The fused step (pixel_step, r3d_pixel.hpp) keeps the pixel's histogram in
+// LDS, evaluates the cost and the prior only on candidate depths, and
+// reduces argmax and moments over the wavefront.
 #include "r3d_device.hpp"
+#include "r3d_pixel.hpp"
 
 namespace r3d {
 
@@ -167,138 +167,27 @@ hipError_t launch_cost_plain(const DevModel& M, const uint16_t* hist, int npix, 
 }
 
 // ---------------------------------------------------------------- a1..a7
+// One wavefront per pixel (pixel_step): photon lists, or histograms whose
+// length the tile kernels do not take.
 template <bool kHist>
 __global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
   extern __shared__ float smem_f[];
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* sh_h = smem_f;
   float* sh_irf = smem_f + M.W;
-  unsigned* hist = reinterpret_cast<unsigned*>(smem_f + 2 * M.W) + (size_t)wave * (M.T + M.D);
-  float* Lb = reinterpret_cast<float*>(hist + M.T);
-  const int p = blockIdx.x * nw + wave;
-  const bool active = p < M.P;
-
+  unsigned* hist = reinterpret_cast<unsigned*>(smem_f + 2 * M.W) + (size_t)wave * ((M.T + 1) >> 1);
   for (int i = threadIdx.x; i < M.W; i += blockDim.x) {
     sh_h[i] = M.h[i];
     sh_irf[i] = M.irf[i];
   }
-  for (int t = lane; t < M.T; t += 64) hist[t] = 0u;
   __syncthreads();
-
-  // a1: histogram of the pixel in LDS
-  const bool faulty = active && io.faulty && io.faulty[p];
-  float K = 0.f;
-  unsigned bad = 0;
-  if (active && !faulty) {
-    if (kHist) {
-      K = load_hist_row(M, io.hist + (size_t)p * M.T, hist, lane, bad);
-    } else {
-      const int b = io.row_ptr[p], e = io.row_ptr[p + 1];
-      if (e < b) bad |= kErrRange;
-      for (int k = b + lane; k < e; k += 64) {
-        const int t = io.toa[k];
-        if ((unsigned)t < (unsigned)M.T)
-          atomicAdd(&hist[t], 1u);
-        else
-          bad |= kErrRange;
-      }
-      K = (float)(e > b ? e - b : 0);
-    }
-  }
-  if (bad) atomicOr(M.err, bad);
-  __syncthreads();
-  if (!active) return;
-
-  // a4: prior components from the previous state of the 3x3 neighbourhood
-  Comps C;
-  build_components(M, io.pm, io.pv, io.ppi, p, C);
-  const unsigned cmask = __builtin_amdgcn_readfirstlane(C.live);  // one pixel per wavefront
-
-  // a3 + a5, first pass: log2 pseudo-posterior on the grid and its argmax
-  float best = -INFINITY;
-  int bi = 0x7fffffff;
-  for (int i = lane; i < M.D; i += 64) {
-    const int d = M.d_lo + i;
-    const float ell = faulty ? 0.f : cost_at(M, sh_h, hist, d);
-    const float L2 = fmaf(ell, M.scale2, log_prior2(C, (float)d, cmask));
-    Lb[i] = L2;
-    if (L2 > best) {
-      best = L2;
-      bi = i;
-    }
-  }
-  group_argmax<1, 32>(best, bi);
-
-  // a5, second pass: weights relative to the maximum, moments centred on d*
-  float S0 = 0.f, S1 = 0.f, S2 = 0.f;
-  for (int i = lane; i < M.D; i += 64) {
-    const float w = fast_exp2(Lb[i] - best);
-    const float e = (float)(i - bi);
-    S0 += w;
-    S1 = fmaf(e, w, S1);
-    S2 = fmaf(e * e, w, S2);
-  }
-  S0 = group_sum<1, 32>(S0);
-  S1 = group_sum<1, 32>(S1);
-  S2 = group_sum<1, 32>(S2);
-  const float mu = S1 / S0;
-  const int dstar = M.d_lo + bi;
-  const float mean = (float)dstar + mu;
-  const float var = fmaxf(S2 / S0 - mu * mu, 0.f);
-
-  // a6 + a7
-  const float pi_now = faulty ? 0.5f : (io.pi_in ? io.pi_in[p] : 1.0f);
-  const bool detected = pi_now > 0.5f;
-  float r_hat = 0.f, b_hat = K / (float)M.T;
-  if (faulty) {
-    b_hat = io.pb[p];
-  } else if (detected) {
-    constexpr int U = kMaxW / 64;
-    float s[U], z[U];
-    float S = 0.f, Kw = 0.f, nw = 0.f;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = lane + 64 * u;
-      const int t = dstar - M.c + j;
-      const bool in = j < M.W && t >= 0 && t < M.T;
-      s[u] = in ? sh_irf[j] : 0.f;
-      z[u] = in ? (float)hist[t] : 0.f;
-      S += s[u];
-      Kw += z[u];
-      nw += in ? 1.f : 0.f;
-    }
-    S = group_sum<1, 32>(S);
-    Kw = group_sum<1, 32>(Kw);
-    nw = group_sum<1, 32>(nw);
-    auto terms = [&](float r, float b, float SoT, float& g1, float& g2) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (z[u] > 0.f) {
-          const float q = (s[u] - SoT) * fast_rcp(fmaf(r, s[u], b));
-          g1 = fmaf(z[u], q, g1);
-          g2 = fmaf(-z[u] * q, q, g2);
-        }
-      }
-    };
-    mle_reflectivity<1, 32>(terms, K, S, Kw, nw, (float)M.T, r_hat, b_hat);
-  }
-
-  if (lane == 0) {
-    io.nm[p] = mean;
-    io.nv[p] = var;
-    io.npi[p] = pi_now;
-    io.nb[p] = b_hat;
-    if (io.depth) io.depth[p] = detected ? mean : __builtin_nanf("");
-    if (io.var) io.var[p] = var;
-    if (io.argmax) io.argmax[p] = dstar;
-    if (io.intensity) io.intensity[p] = r_hat;
-    if (io.background) io.background[p] = b_hat;
-    if (io.pi0_next) io.pi0_next[p] = pi0_next_at(M, io.pi_in, io.faulty, p);
-  }
+  const int p = blockIdx.x * nw + wave;
+  if (p >= M.P) return;
+  pixel_step<kHist>(M, io, p, lane, hist, sh_h, sh_irf);
 }
 
 static size_t step_plain_fixed(const DevModel& M) { return (size_t)M.W * 8; }
-static size_t step_plain_per_wave(const DevModel& M) { return (size_t)(M.T + M.D) * 4; }
+static size_t step_plain_per_wave(const DevModel& M) { return (size_t)((M.T + 1) >> 1) * 4; }
 
 bool plain_supported(const DevModel& M) {
   return waves_for(step_plain_per_wave(M), step_plain_fixed(M)) > 0;

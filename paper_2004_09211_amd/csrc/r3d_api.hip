@@ -5,10 +5,12 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "r3d_internal.hpp"
 #include "r3d_tile.hpp"
+#include "r3d_batch.hpp"
 
 struct r3d_ctx {
   int device = 0;
@@ -120,6 +122,7 @@ const char* r3d_status_string(r3d_status s) {
     case R3D_ENOMEM: return "device allocation failed";
     case R3D_EHIP: return "HIP runtime error";
     case R3D_EUNSUPPORTED: return "unsupported size or option";
+    case R3D_ETIMEDOUT: return "a batched work item waited past its spin limit";
   }
   return "unknown status";
 }
@@ -171,6 +174,9 @@ r3d_status r3d_create(const r3d_params* params, r3d_ctx** out) {
   m.W = W;
   m.c = params->c;
   m.scale2 = (float)((params->beta + 1.0) / params->beta * 1.4426950408889634);
+  double hmax = 0.0;
+  for (int j = 0; j < W; ++j) hmax = std::fmax(hmax, std::pow(c->irf[j], params->beta));
+  m.hmax = (float)(hmax * (1.0 + 1e-6));
   m.m_flat = (float)(0.5 * (params->d_min + params->d_max));
   const double span = params->d_max - params->d_min;
   m.v_flat = (float)(span * span / 12.0);
@@ -247,6 +253,173 @@ r3d_status r3d_step_hist(r3d_ctx* ctx, const uint16_t* hist, const float* pi_in,
   return hip_status(r3d::launch_step_plain(ctx->dm, io, true, (hipStream_t)stream));
 }
 
+}  // extern "C"
+
+struct r3d_batch {
+  r3d::SeqDesc* d_seqs = nullptr;
+  int* d_prefix = nullptr;
+  void** d_ptrs = nullptr;  // every sequence's row_ptr and toa pointer arrays
+  unsigned* d_queue = nullptr;
+  int* d_done = nullptr;
+  unsigned* d_err = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_batch(r3d_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->d_seqs) (void)hipFree(b->d_seqs);
+  if (b->d_prefix) (void)hipFree(b->d_prefix);
+  if (b->d_ptrs) (void)hipFree(b->d_ptrs);
+  if (b->d_queue) (void)hipFree(b->d_queue);
+  if (b->d_done) (void)hipFree(b->d_done);
+  if (b->d_err) (void)hipFree(b->d_err);
+  delete b;
+}
+
+r3d_status device_bits(unsigned bits) {
+  if (bits & r3d::kErrTimeout) return R3D_ETIMEDOUT;
+  if (bits & r3d::kErrRange) return R3D_ERANGE;
+  if (bits & r3d::kErrOverflow) return R3D_EOVERFLOW;
+  return R3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq, uint32_t spin_limit,
+                            r3d_batch** out) {
+  if (!out) return R3D_EINVAL;
+  *out = nullptr;
+  if (!seqs || nseq < 1) return R3D_EINVAL;
+  std::vector<r3d::SeqDesc> host(nseq);
+  std::vector<int> prefix(nseq + 1, 0);
+  std::vector<void*> ptrs;
+  int tmax = 1, fmax = 1;
+  for (int s = 0; s < nseq; ++s) {
+    const r3d_sequence& q = seqs[s];
+    if (!q.ctx || q.nframes < 1 || !q.row_ptr || !q.toa || q.chunk_rows < 0) return R3D_EINVAL;
+    if (check_state(&q.state[0]) != R3D_OK || check_state(&q.state[1]) != R3D_OK) return R3D_EINVAL;
+    if (same_buffer(&q.state[0], &q.state[1])) return R3D_EINVAL;
+    if (q.ctx->prm.precision != R3D_FP32) return R3D_EUNSUPPORTED;
+    for (int n = 0; n < q.nframes; ++n)
+      if (!q.row_ptr[n] || !q.toa[n]) return R3D_EINVAL;
+    const r3d::DevModel& M = q.ctx->dm;
+    r3d::SeqDesc& d = host[s];
+    d.M = M;
+    d.nframes = q.nframes;
+    d.chunk_rows = q.chunk_rows > 0 ? q.chunk_rows : (256 + M.cols - 1) / M.cols;
+    if (d.chunk_rows > M.rows) d.chunk_rows = M.rows;
+    d.nchunks = (M.rows + d.chunk_rows - 1) / d.chunk_rows;
+    d.done_off = prefix[s];
+    prefix[s + 1] = prefix[s] + d.nchunks;
+    d.row_ptr = reinterpret_cast<const int32_t* const*>(ptrs.size());  // offset, fixed below
+    for (int n = 0; n < q.nframes; ++n) ptrs.push_back((void*)q.row_ptr[n]);
+    d.toa = reinterpret_cast<const int16_t* const*>(ptrs.size());
+    for (int n = 0; n < q.nframes; ++n) ptrs.push_back((void*)q.toa[n]);
+    for (int i = 0; i < 2; ++i) {
+      d.st_m[i] = q.state[i].m;
+      d.st_v[i] = q.state[i].v;
+      d.st_pi[i] = q.state[i].pi;
+      d.st_b[i] = q.state[i].b;
+    }
+    d.depth = q.out.depth;
+    d.var = q.out.var;
+    d.intensity = q.out.intensity;
+    d.background = q.out.background;
+    d.pi0_next = q.out.pi0_next;
+    d.argmax = q.out.argmax;
+    d.pi_in = q.pi_in;
+    d.faulty = q.faulty;
+    tmax = std::max(tmax, M.T);
+    fmax = std::max(fmax, q.nframes);
+  }
+  r3d::BatchGeom G{};
+  G.nseq = nseq;
+  G.chunks_total = prefix[nseq];
+  G.hist_words = (tmax + 1) / 2;
+  if (r3d::batch_lds_bytes(G) > 65536) return R3D_EUNSUPPORTED;
+  const long long nitems = (long long)fmax * G.chunks_total;
+  if (nitems >= (1LL << 31)) return R3D_EUNSUPPORTED;
+  G.nitems = (unsigned)nitems;
+  G.spin_limit = spin_limit ? spin_limit : (1u << 22);
+  G.ndone = G.chunks_total;
+
+  r3d_batch* b = new (std::nothrow) r3d_batch();
+  if (!b) return R3D_ENOMEM;
+  if (hipMalloc(&b->d_seqs, nseq * sizeof(r3d::SeqDesc)) != hipSuccess ||
+      hipMalloc(&b->d_prefix, (nseq + 1) * sizeof(int)) != hipSuccess ||
+      hipMalloc(&b->d_ptrs, ptrs.size() * sizeof(void*)) != hipSuccess ||
+      hipMalloc(&b->d_queue, sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&b->d_done, G.ndone * sizeof(int)) != hipSuccess ||
+      hipMalloc(&b->d_err, sizeof(unsigned)) != hipSuccess) {
+    free_batch(b);
+    return R3D_ENOMEM;
+  }
+  for (auto& d : host) {  // turn pointer-array offsets into device addresses
+    d.row_ptr = reinterpret_cast<const int32_t* const*>(b->d_ptrs + (size_t)d.row_ptr);
+    d.toa = reinterpret_cast<const int16_t* const*>(b->d_ptrs + (size_t)d.toa);
+  }
+  G.chunk_prefix = b->d_prefix;
+  G.queue = b->d_queue;
+  G.done = b->d_done;
+  G.err = b->d_err;
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_seqs, host.data(), nseq * sizeof(r3d::SeqDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_prefix, prefix.data(), (nseq + 1) * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(b->d_err, 0, sizeof(unsigned));
+  const int blocks = std::max(1, ncu) * r3d::batch_blocks_per_cu(G);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = r3d::launch_batch(b->d_seqs, G, blocks, b->cap);
+    e = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_batch(b);
+    return R3D_EHIP;
+  }
+  *out = b;
+  return R3D_OK;
+}
+
+r3d_status r3d_batch_launch(r3d_batch* b, void* stream) {
+  if (!b) return R3D_EINVAL;
+  return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? R3D_OK : R3D_EHIP;
+}
+
+r3d_status r3d_batch_status(r3d_batch* b, void* stream) {
+  if (!b) return R3D_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return R3D_EHIP;
+  unsigned bits = 0;
+  if (hipMemcpy(&bits, b->d_err, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
+    return R3D_EHIP;
+  if (hipMemset(b->d_err, 0, sizeof(unsigned)) != hipSuccess) return R3D_EHIP;
+  return device_bits(bits);
+}
+
+void r3d_batch_destroy(r3d_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+}
+
 r3d_status r3d_last_device_status(r3d_ctx* ctx, void* stream) {
   if (!ctx) return R3D_EINVAL;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return R3D_EHIP;
@@ -254,9 +427,7 @@ r3d_status r3d_last_device_status(r3d_ctx* ctx, void* stream) {
   if (hipMemcpy(&bits, ctx->d_err, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
     return R3D_EHIP;
   if (hipMemset(ctx->d_err, 0, sizeof(unsigned)) != hipSuccess) return R3D_EHIP;
-  if (bits & r3d::kErrRange) return R3D_ERANGE;
-  if (bits & r3d::kErrOverflow) return R3D_EOVERFLOW;
-  return R3D_OK;
+  return device_bits(bits);
 }
 
 }  // extern "C"

@@ -15,13 +15,14 @@ constexpr int kMaxW = 256;
 constexpr float kMaxFp16Count = 2048.0f;  // largest count fp16 holds exactly with all below
 
 // error bits of the device error word
-enum : unsigned { kErrRange = 1u, kErrOverflow = 2u };
+enum : unsigned { kErrRange = 1u, kErrOverflow = 2u, kErrTimeout = 4u };
 
 // Model in the form the kernels use; passed by value as a kernel argument.
 // Log-quantities are in base 2 (the hardware exp/log are base 2).
 struct DevModel {
   int rows, cols, P, T, d_lo, D, W, c;
   float scale2;      // (beta+1)/beta * log2(e): cost in log2 units
+  float hmax;        // an upper bound of max_j irf^beta[j] (for the culling bound)
   float m_flat;      // (d_min+d_max)/2
   float v_flat;      // (d_max-d_min)^2/12
   float sigma_rw2;   // random-walk variance

@@ -22,7 +22,9 @@ R3D_FP32, R3D_FP16_MFMA, R3D_FP16X2_MFMA = 0, 1, 2
 PRECISIONS = {"fp32": R3D_FP32, "fp16": R3D_FP16_MFMA, "fp16x2": R3D_FP16X2_MFMA}
 
 STATUS = {0: "R3D_OK", -1: "R3D_EINVAL", -2: "R3D_ERANGE", -3: "R3D_EOVERFLOW",
-          -4: "R3D_ENOMEM", -5: "R3D_EHIP", -6: "R3D_EUNSUPPORTED"}
+          -4: "R3D_ENOMEM", -5: "R3D_EHIP", -6: "R3D_EUNSUPPORTED", -7: "R3D_ETIMEDOUT"}
+
+STATUS_CODES = {v: k for k, v in STATUS.items()}
 
 
 class Params(ctypes.Structure):
@@ -42,6 +44,12 @@ class COut(ctypes.Structure):
                 ("background", c_void_p), ("pi0_next", c_void_p), ("argmax", c_void_p)]
 
 
+class CSequence(ctypes.Structure):
+    _fields_ = [("ctx", c_void_p), ("nframes", c_int32), ("row_ptr", POINTER(c_void_p)),
+                ("toa", POINTER(c_void_p)), ("state", CState * 2), ("out", COut),
+                ("pi_in", c_void_p), ("faulty", c_void_p), ("chunk_rows", c_int32)]
+
+
 #: every symbol the header declares, with (restype, argtypes)
 SIGNATURES = {
     "r3d_create": (c_int32, [POINTER(Params), POINTER(c_void_p)]),
@@ -54,6 +62,11 @@ SIGNATURES = {
     "r3d_step_hist": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                 POINTER(CState), POINTER(CState), POINTER(COut), c_void_p]),
     "r3d_last_device_status": (c_int32, [c_void_p, c_void_p]),
+    "r3d_batch_create": (c_int32, [POINTER(CSequence), c_int32, ctypes.c_uint32,
+                                   POINTER(c_void_p)]),
+    "r3d_batch_launch": (c_int32, [c_void_p, c_void_p]),
+    "r3d_batch_status": (c_int32, [c_void_p, c_void_p]),
+    "r3d_batch_destroy": (None, [c_void_p]),
     "r3d_status_string": (c_char_p, [c_int32]),
 }
 
@@ -258,3 +271,79 @@ class R3DFilter:
             self.ctx.step_csr(row_ptr, toa, self.prev, self.next, out, pi_in, faulty)
         self.prev, self.next = self.next, self.prev
         return out
+
+
+@dataclass
+class Sequence:
+    """One sequence of a batch: its context, its photon-list frames (device
+    (row_ptr, toa) pairs), two state buffers (frame n reads ``states[n % 2]``)
+    and frame-major outputs of ``nframes * P`` elements."""
+    ctx: Context
+    frames: list
+    states: tuple
+    out: Outputs
+    pi_in: Optional[torch.Tensor] = None
+    faulty: Optional[torch.Tensor] = None
+    chunk_rows: int = 0
+
+    @classmethod
+    def allocate(cls, ctx: Context, frames, device="cuda", **kw) -> "Sequence":
+        P = ctx.P
+        st = (State.empty(P, device), State.empty(P, device))
+        out = Outputs.empty(len(frames) * P, device)
+        return cls(ctx, list(frames), st, out, **kw)
+
+    @property
+    def final_state(self) -> State:
+        return self.states[len(self.frames) % 2]
+
+    def init_state(self, stream=None):
+        self.ctx.state_init(self.states[0], stream)
+
+
+class Batch:
+    """An r3d_batch: many sequences in one persistent launch, captured once
+    into a graph and replayed by ``launch``."""
+
+    def __init__(self, seqs, spin_limit: int = 0):
+        lib = load()
+        self.seqs = list(seqs)
+        arr = (CSequence * len(self.seqs))()
+        self._keep = []
+        for i, q in enumerate(self.seqs):
+            n = len(q.frames)
+            rp = (c_void_p * n)(*[_ptr(f[0], torch.int32) for f in q.frames])
+            ta = (c_void_p * n)(*[_ptr(f[1], torch.int16) for f in q.frames])
+            self._keep += [rp, ta]
+            a = arr[i]
+            a.ctx = q.ctx._h
+            a.nframes = n
+            a.row_ptr = ctypes.cast(rp, POINTER(c_void_p))
+            a.toa = ctypes.cast(ta, POINTER(c_void_p))
+            a.state[0] = q.states[0].c()
+            a.state[1] = q.states[1].c()
+            a.out = q.out.c()
+            a.pi_in = _ptr(q.pi_in, torch.float32)
+            a.faulty = _ptr(q.faulty, torch.uint8)
+            a.chunk_rows = int(q.chunk_rows)
+        h = c_void_p()
+        _check(lib.r3d_batch_create(arr, len(self.seqs), int(spin_limit), byref(h)),
+               "r3d_batch_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_lib.r3d_batch_launch(self._h, _stream(stream)), "r3d_batch_launch")
+
+    def status(self, stream=None) -> int:
+        return int(_lib.r3d_batch_status(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.r3d_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

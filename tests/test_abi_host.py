@@ -64,7 +64,7 @@ int main(void) {
 
 def test_status_strings(r3d):
     lib = r3d.load()
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = lib.r3d_status_string(code).decode()
         assert s and s != "unknown status"
     assert lib.r3d_status_string(42).decode() == "unknown status"
@@ -120,6 +120,46 @@ def test_null_context_and_pointers_rejected(r3d):
     assert lib.r3d_cost(None, None, 0, None, None) == -1
     assert lib.r3d_last_device_status(None, None) == -1
     lib.r3d_destroy(None)
+
+
+def test_batch_entry_points_reject_bad_arguments(r3d):
+    lib = r3d.load()
+    h = ctypes.c_void_p()
+    assert lib.r3d_batch_create(None, 1, 0, ctypes.byref(h)) == -1
+    seqs = (r3d.CSequence * 1)()
+    assert lib.r3d_batch_create(seqs, 0, 0, ctypes.byref(h)) == -1
+    assert lib.r3d_batch_create(seqs, 1, 0, ctypes.byref(h)) == -1  # NULL context
+    assert lib.r3d_batch_create(seqs, 1, 0, None) == -1
+    assert not h.value
+    assert lib.r3d_batch_launch(None, None) == -1
+    assert lib.r3d_batch_status(None, None) == -1
+    lib.r3d_batch_destroy(None)
+
+
+def test_sequence_layout_matches_c(tmp_path, r3d):
+    src = tmp_path / "seq.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "r3d.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(r3d_sequence),
+         offsetof(r3d_sequence, nframes), offsetof(r3d_sequence, row_ptr),
+         offsetof(r3d_sequence, toa), offsetof(r3d_sequence, state),
+         offsetof(r3d_sequence, out), offsetof(r3d_sequence, pi_in),
+         offsetof(r3d_sequence, faulty), offsetof(r3d_sequence, chunk_rows));
+  return 0;
+}
+""")
+    exe = tmp_path / "seq"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    S = r3d.CSequence
+    want = [ctypes.sizeof(S)] + [getattr(S, f).offset for f in
+                                 ("nframes", "row_ptr", "toa", "state", "out", "pi_in", "faulty",
+                                  "chunk_rows")]
+    assert got == want
 
 
 def test_binding_refuses_missing_library(tmp_path):
