@@ -128,6 +128,77 @@ def run_gpu(args):
     return res, sample_hist
 
 
+def run_batched(args):
+    """Uneven batch: 64 sequences x 10 frames (resolutions 32..256 squared,
+    500..4000 bins, log-normal photon counts) through one persistent launch
+    replayed from a captured graph, launch shape from the autotuner (tuned
+    before timing); compared with the per-frame entry point launched once per
+    sequence and frame on the same inputs."""
+    import torch
+    import synth
+    from paper_2004_09211_amd import r3d, tune
+
+    dev = torch.device("cuda:0")
+    wls = synth.config3(seed=0, device=dev)
+    torch.cuda.synchronize()
+    seqs = [r3d.Sequence.allocate(r3d.Context(w.params()), [(f.row_ptr, f.toa) for f in w.frames],
+                                  dev) for w in wls]
+
+    def reset():
+        for q in seqs:
+            q.init_state()
+
+    cfg = tune.tune(seqs, reset, reps=1, cache=args.tune_cache or None)
+    batch = r3d.Batch(seqs, blocks=cfg["blocks"])
+    times = []
+    for i in range(args.batched_reps + 1):
+        reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        batch.launch()
+        e1.record()
+        status = batch.status()
+        if status != 0:
+            raise RuntimeError(f"batch status {status}")
+        if i > 0:
+            times.append(e0.elapsed_time(e1))
+    batch.close()
+    pf = sum(w.P * len(w.frames) for w in wls)
+    ms = sorted(times)[len(times) // 2]
+    # per-frame launches of the same step on the same inputs
+    st = [(r3d.State.empty(q.ctx.P, dev), r3d.State.empty(q.ctx.P, dev)) for q in seqs]
+    outs = [r3d.Outputs.empty(q.ctx.P, dev) for q in seqs]
+    pms = []
+    for i in range(2):
+        for q, s2 in zip(seqs, st):
+            q.ctx.state_init(s2[0])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for n in range(max(len(w.frames) for w in wls)):
+            for q, w, s2, o in zip(seqs, wls, st, outs):
+                if n < len(w.frames):
+                    q.ctx.step_csr(*q.frames[n], s2[n % 2], s2[(n + 1) % 2], o)
+        e1.record()
+        torch.cuda.synchronize()
+        if i > 0:
+            pms.append(e0.elapsed_time(e1))
+    for q in seqs:
+        if q.ctx.last_device_status() != 0:
+            raise RuntimeError("per-frame path reported a device error")
+    photons = sum(int(f.row_ptr[-1]) for w in wls for f in w.frames)
+    return dict(value=round(pf / (ms * 1e-3), 1), unit="pixel-frames/s", ms_per_pass=round(ms, 3),
+                pixel_frames=pf, photons=photons,
+                per_frame_launches=dict(value=round(pf / (pms[0] * 1e-3), 1),
+                                        ms_per_pass=round(pms[0], 3)),
+                speedup_vs_per_frame=round(pms[0] / ms, 3),
+                tuned={k: cfg[k] for k in ("item_px", "balanced", "blocks")},
+                workload="64 uneven sequences x 10 frames (32..256 squared, T 500..4000, "
+                         "log-normal photon counts, fp32 photon lists)")
+
+
 def cpu_baseline(params, sample_hist, rows):
     import numpy as np
     import oracle
@@ -155,6 +226,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=20)
     ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=5)
+    ap.add_argument("--tune-cache", default="")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is measured on a single MI355X "
@@ -163,6 +237,7 @@ def main():
         sys.exit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     res, sample = run_gpu(args)
+    batched = None if args.no_batched else run_batched(args)
     cpu = cpu_baseline(res["params"], sample, args.cpu_rows) if sample is not None else None
     line = dict(
         metric=METRIC, value=round(res["value"], 1), unit="pixel-frames/s", n_gpus=1,
@@ -178,7 +253,7 @@ def main():
                     dict(value=round(res["plain"]["value"], 1),
                          ms_per_step=round(res["plain"]["ms_per_step"], 3),
                          speedup=round(res["value"] / res["plain"]["value"], 3))),
-        roofline=res["roofline"], cpu_baseline=cpu)
+        roofline=res["roofline"], cpu_baseline=cpu, batched=batched)
     print(json.dumps(line), flush=True)
 
 

@@ -182,14 +182,22 @@ typedef struct {
 
 typedef struct r3d_batch r3d_batch;
 
+/* Launch options of a batch; a NULL pointer or zero fields take defaults. */
+typedef struct {
+    uint32_t spin_limit;  /* dependency polls per item before R3D_ETIMEDOUT is
+                             recorded and the item proceeds (0 = a default far
+                             above any legitimate wait)                         */
+    int32_t blocks;       /* persistent workgroups (0 = compute units times the
+                             workgroups that fit on one)                        */
+} r3d_batch_options;
+
 /* Validate the sequences, upload their descriptors (the pointers are kept:
  * the caller's buffers must stay allocated while the batch exists), size the
- * work queue and capture the launch into a graph. spin_limit bounds the
- * dependency polls of one item (0 = a default far above any legitimate
- * wait); an exhausted limit records R3D_ETIMEDOUT and the item proceeds.
- * Synchronous. Histogram lengths up to 7936 bins. */
-r3d_status r3d_batch_create(const r3d_sequence *seqs, int32_t nseq, uint32_t spin_limit,
-                            r3d_batch **out);
+ * work queue and capture the launch into a graph. Synchronous. Histogram
+ * lengths up to 7468 bins; R3D_EUNSUPPORTED for longer ones or a context
+ * whose precision is not R3D_FP32. */
+r3d_status r3d_batch_create(const r3d_sequence *seqs, int32_t nseq,
+                            const r3d_batch_options *opt, r3d_batch **out);
 
 /* Replay the captured launch on the stream (asynchronous). */
 r3d_status r3d_batch_launch(r3d_batch *batch, void *stream);

@@ -27,7 +27,7 @@ __global__ void k_batch_reset(unsigned* queue, int* done, int ndone) {
 }
 
 __global__ void __launch_bounds__(256) k_batch(const SeqDesc* __restrict__ seqs, BatchGeom B) {
-  extern __shared__ float smem[];
+  extern __shared__ __align__(16) float smem[];
   __shared__ unsigned s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // wave-uniform predicate (readfirstlane), so every branch that brackets a

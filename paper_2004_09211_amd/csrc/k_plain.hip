@@ -171,11 +171,12 @@ hipError_t launch_cost_plain(const DevModel& M, const uint16_t* hist, int npix, 
 // length the tile kernels do not take.
 template <bool kHist>
 __global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
-  extern __shared__ float smem_f[];
+  extern __shared__ __align__(16) float smem_f[];
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* sh_h = smem_f;
   float* sh_irf = smem_f + M.W;
-  unsigned* hist = reinterpret_cast<unsigned*>(smem_f + 2 * M.W) + (size_t)wave * ((M.T + 1) >> 1);
+  unsigned* hist = reinterpret_cast<unsigned*>(smem_f + ((2 * M.W + 3) & ~3)) +
+                   (size_t)wave * pixel_lds_words(M.T);
   for (int i = threadIdx.x; i < M.W; i += blockDim.x) {
     sh_h[i] = M.h[i];
     sh_irf[i] = M.irf[i];
@@ -186,8 +187,8 @@ __global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
   pixel_step<kHist>(M, io, p, lane, hist, sh_h, sh_irf);
 }
 
-static size_t step_plain_fixed(const DevModel& M) { return (size_t)M.W * 8; }
-static size_t step_plain_per_wave(const DevModel& M) { return (size_t)((M.T + 1) >> 1) * 4; }
+static size_t step_plain_fixed(const DevModel& M) { return (size_t)((2 * M.W + 3) & ~3) * 4; }
+static size_t step_plain_per_wave(const DevModel& M) { return (size_t)pixel_lds_words(M.T) * 4; }
 
 bool plain_supported(const DevModel& M) {
   return waves_for(step_plain_per_wave(M), step_plain_fixed(M)) > 0;

@@ -11,6 +11,7 @@
 #include "r3d_internal.hpp"
 #include "r3d_tile.hpp"
 #include "r3d_batch.hpp"
+#include "r3d_pixel.hpp"
 
 struct r3d_ctx {
   int device = 0;
@@ -294,11 +295,14 @@ r3d_status device_bits(unsigned bits) {
 
 extern "C" {
 
-r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq, uint32_t spin_limit,
-                            r3d_batch** out) {
+r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq,
+                            const r3d_batch_options* opt, r3d_batch** out) {
   if (!out) return R3D_EINVAL;
   *out = nullptr;
   if (!seqs || nseq < 1) return R3D_EINVAL;
+  const uint32_t spin_limit = opt ? opt->spin_limit : 0u;
+  const int req_blocks = opt ? opt->blocks : 0;
+  if (req_blocks < 0) return R3D_EINVAL;
   std::vector<r3d::SeqDesc> host(nseq);
   std::vector<int> prefix(nseq + 1, 0);
   std::vector<void*> ptrs;
@@ -344,7 +348,7 @@ r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq, uint32_t spi
   r3d::BatchGeom G{};
   G.nseq = nseq;
   G.chunks_total = prefix[nseq];
-  G.hist_words = (tmax + 1) / 2;
+  G.hist_words = r3d::pixel_lds_words(tmax);
   if (r3d::batch_lds_bytes(G) > 65536) return R3D_EUNSUPPORTED;
   const long long nitems = (long long)fmax * G.chunks_total;
   if (nitems >= (1LL << 31)) return R3D_EUNSUPPORTED;
@@ -381,7 +385,7 @@ r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq, uint32_t spi
   if (e == hipSuccess)
     e = hipMemcpy(b->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(b->d_err, 0, sizeof(unsigned));
-  const int blocks = std::max(1, ncu) * r3d::batch_blocks_per_cu(G);
+  const int blocks = req_blocks > 0 ? req_blocks : std::max(1, ncu) * r3d::batch_blocks_per_cu(G);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {

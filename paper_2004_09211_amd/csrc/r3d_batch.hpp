@@ -29,7 +29,7 @@ struct BatchGeom {
   int chunks_total;        // sum of nchunks
   const int* chunk_prefix;  // device [nseq + 1]
   unsigned nitems;         // max frames * chunks_total
-  int hist_words;          // LDS words per wavefront ((max T + 1) / 2)
+  int hist_words;          // LDS words per wavefront (pixel_lds_words of the largest T)
   unsigned spin_limit;     // bound on dependency polls per item
   unsigned* queue;         // work counter
   int* done;               // [ndone] frames completed per (sequence, chunk)

@@ -2,7 +2,8 @@
 // histograms of any length: the per-pixel step shared by the single-frame
 // photon-list kernel and the persistent batched kernel.
 //
-// The histogram is built in LDS as 16-bit counts packed two per word. The
+// The histogram is built in LDS as 16-bit counts packed two per word, and
+// for photon lists also as one bit per bin marking the non-empty bins. The
 // cost is only evaluated on candidate depths: since the cost is non-negative
 // and at most scale * max(irf^beta) * K, and the log prior at the mean of one
 // of its components is a lower bound of the best log pseudo-posterior, every
@@ -12,6 +13,12 @@
 // zero weight and cannot be the argmax. Lanes walk the candidate range 64
 // depths at a time (chunks that meet no component interval are skipped),
 // keep online centred moments, and the wavefront merges them at the end.
+//
+// Cost gather: ell(d) sums irf^beta[j] * z[d - c + j] over the taps in
+// increasing j. With few photons per bin range (3K <= T) the sum walks only
+// the set bits of the non-empty-bin mask inside the window, in increasing
+// bin order; the skipped terms are exact zeros (fma(h, 0, ell) == ell), so
+// both gathers give the same bits.
 #pragma once
 
 #include "r3d_device.hpp"
@@ -28,20 +35,32 @@ __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// LDS words one wavefront needs for a pixel of T bins: packed 16-bit counts
+// then the non-empty-bin mask, rounded up to whole 16-byte vectors.
+__host__ __device__ constexpr int pixel_lds_words(int T) {
+  return ((((T + 1) >> 1) + ((T + 31) >> 5)) + 3) & ~3;
+}
+
 // count of bin t in the packed LDS histogram
 __device__ __forceinline__ float packed_count(const unsigned* hist, int t) {
   return (float)((hist[t >> 1] >> ((t & 1) << 4)) & 0xffffu);
 }
 
-// Per-pixel step. ``hist`` is this wavefront's LDS region of (T + 1) / 2
-// words; ``sh_h`` and ``sh_irf`` hold irf^beta and irf (W floats each).
+// Per-pixel step. ``hist`` is this wavefront's 16-byte aligned LDS region of
+// pixel_lds_words(T) words; ``sh_h`` and ``sh_irf`` hold irf^beta and irf
+// (W floats each).
 template <bool kHist>
 __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, int p, int lane,
                                            unsigned* hist, const float* sh_h,
                                            const float* sh_irf) {
   const int nwords = (M.T + 1) >> 1;
-  for (int w = lane; w < nwords; w += 64) hist[w] = 0u;
-  wave_fence();
+  unsigned* nzmask = hist + nwords;
+  if constexpr (!kHist) {
+    uint4* z4 = reinterpret_cast<uint4*>(hist);
+    const int n4 = pixel_lds_words(M.T) >> 2;
+    for (int w = lane; w < n4; w += 64) z4[w] = make_uint4(0u, 0u, 0u, 0u);
+    wave_fence();
+  }
 
   // ---- a1: histogram of the pixel ----
   const bool faulty = io.faulty && io.faulty[p];
@@ -74,9 +93,10 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
       if (e - b > 65535) bad |= kErrOverflow;  // 16-bit bins could overflow
       for (int k = b + lane; k < e; k += 64) {
         const int t = io.toa[k];
-        if ((unsigned)t < (unsigned)M.T)
+        if ((unsigned)t < (unsigned)M.T) {
           atomicAdd(&hist[t >> 1], 1u << ((t & 1) << 4));
-        else
+          atomicOr(&nzmask[t >> 5], 1u << (t & 31));
+        } else
           bad |= kErrRange;
       }
       K = (float)(e > b ? e - b : 0);
@@ -122,6 +142,7 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
   }
 
   // ---- a3 + a5 on the candidates: online centred moments per lane ----
+  const bool sparse = !kHist && 3.f * K <= (float)M.T;  // wave-uniform
   float Rm = -INFINITY, S0 = 0.f, S1 = 0.f, S2 = 0.f, ref = 0.f;
   for (int d0 = dlo_c; d0 <= dhi_c; d0 += 64) {
     const float dc = (float)d0 + 31.5f;
@@ -138,9 +159,25 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
     float ell = 0.f;
     if (!faulty) {
       const int t0 = d - M.c;
-      const int jlo = t0 < 0 ? -t0 : 0;
-      const int jhi = (M.T - t0) < M.W ? (M.T - t0) : M.W;
-      for (int j = jlo; j < jhi; ++j) ell = fmaf(sh_h[j], packed_count(hist, t0 + j), ell);
+      if (sparse) {
+        const int lo = t0 > 0 ? t0 : 0;
+        const int hi = (t0 + M.W) < M.T ? (t0 + M.W) : M.T;
+        for (int t = lo; t < hi;) {
+          const int base = t & ~31;
+          unsigned bits = nzmask[base >> 5] & (~0u << (t - base));
+          if (hi - base < 32) bits &= (1u << (hi - base)) - 1u;
+          while (bits) {
+            const int tb = base + __builtin_ctz(bits);
+            bits &= bits - 1u;
+            ell = fmaf(sh_h[tb - t0], packed_count(hist, tb), ell);
+          }
+          t = base + 32;
+        }
+      } else {
+        const int jlo = t0 < 0 ? -t0 : 0;
+        const int jhi = (M.T - t0) < M.W ? (M.T - t0) : M.W;
+        for (int j = jlo; j < jhi; ++j) ell = fmaf(sh_h[j], packed_count(hist, t0 + j), ell);
+      }
     }
     const float L2 = fmaf(ell, M.scale2, log_prior2(C, (float)d, cmask));
     if (L2 > Rm) {

@@ -50,6 +50,10 @@ class CSequence(ctypes.Structure):
                 ("pi_in", c_void_p), ("faulty", c_void_p), ("chunk_rows", c_int32)]
 
 
+class CBatchOptions(ctypes.Structure):
+    _fields_ = [("spin_limit", ctypes.c_uint32), ("blocks", c_int32)]
+
+
 #: every symbol the header declares, with (restype, argtypes)
 SIGNATURES = {
     "r3d_create": (c_int32, [POINTER(Params), POINTER(c_void_p)]),
@@ -62,7 +66,7 @@ SIGNATURES = {
     "r3d_step_hist": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                 POINTER(CState), POINTER(CState), POINTER(COut), c_void_p]),
     "r3d_last_device_status": (c_int32, [c_void_p, c_void_p]),
-    "r3d_batch_create": (c_int32, [POINTER(CSequence), c_int32, ctypes.c_uint32,
+    "r3d_batch_create": (c_int32, [POINTER(CSequence), c_int32, POINTER(CBatchOptions),
                                    POINTER(c_void_p)]),
     "r3d_batch_launch": (c_int32, [c_void_p, c_void_p]),
     "r3d_batch_status": (c_int32, [c_void_p, c_void_p]),
@@ -187,6 +191,7 @@ class Context:
         h = c_void_p()
         _check(lib.r3d_create(byref(prm), byref(h)), "r3d_create")
         self._h = h
+        self.rows, self.cols = prm.rows, prm.cols
         self.P = prm.rows * prm.cols
         self.T, self.D = prm.T, prm.D
         self.precision = prm.precision
@@ -305,7 +310,7 @@ class Batch:
     """An r3d_batch: many sequences in one persistent launch, captured once
     into a graph and replayed by ``launch``."""
 
-    def __init__(self, seqs, spin_limit: int = 0):
+    def __init__(self, seqs, spin_limit: int = 0, blocks: int = 0):
         lib = load()
         self.seqs = list(seqs)
         arr = (CSequence * len(self.seqs))()
@@ -326,8 +331,9 @@ class Batch:
             a.pi_in = _ptr(q.pi_in, torch.float32)
             a.faulty = _ptr(q.faulty, torch.uint8)
             a.chunk_rows = int(q.chunk_rows)
+        opt = CBatchOptions(int(spin_limit), int(blocks))
         h = c_void_p()
-        _check(lib.r3d_batch_create(arr, len(self.seqs), int(spin_limit), byref(h)),
+        _check(lib.r3d_batch_create(arr, len(self.seqs), byref(opt), byref(h)),
                "r3d_batch_create")
         self._h = h
 

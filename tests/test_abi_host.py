@@ -125,11 +125,13 @@ def test_null_context_and_pointers_rejected(r3d):
 def test_batch_entry_points_reject_bad_arguments(r3d):
     lib = r3d.load()
     h = ctypes.c_void_p()
-    assert lib.r3d_batch_create(None, 1, 0, ctypes.byref(h)) == -1
+    assert lib.r3d_batch_create(None, 1, None, ctypes.byref(h)) == -1
     seqs = (r3d.CSequence * 1)()
-    assert lib.r3d_batch_create(seqs, 0, 0, ctypes.byref(h)) == -1
-    assert lib.r3d_batch_create(seqs, 1, 0, ctypes.byref(h)) == -1  # NULL context
-    assert lib.r3d_batch_create(seqs, 1, 0, None) == -1
+    assert lib.r3d_batch_create(seqs, 0, None, ctypes.byref(h)) == -1
+    assert lib.r3d_batch_create(seqs, 1, None, ctypes.byref(h)) == -1  # NULL context
+    assert lib.r3d_batch_create(seqs, 1, None, None) == -1
+    bad = r3d.CBatchOptions(0, -3)
+    assert lib.r3d_batch_create(seqs, 1, ctypes.byref(bad), ctypes.byref(h)) == -1
     assert not h.value
     assert lib.r3d_batch_launch(None, None) == -1
     assert lib.r3d_batch_status(None, None) == -1

@@ -188,3 +188,29 @@ def test_full_uneven_workload(lib):
         sub = {k: v[targets] for k, v in batch_outputs(seqs[i], last).items()}
         sub["mean"] = sub["depth"]  # no detection input: every pixel is detected
         compare(sub, ref, mean_rel=1e-3, var_rel=1e-2, int_rel=1e-2, label=f"seq {i} sample")
+
+
+def test_autotuner_picks_a_shape_and_caches_it(lib, tmp_path):
+    """Every candidate shape gives the same bits; the tuned one is reused
+    from the cache by a second call."""
+    from paper_2004_09211_amd import tune
+    wls = small_batch()
+    seqs = make_sequences(lib, wls)
+
+    def reset():
+        for q in seqs:
+            q.init_state()
+
+    cache = str(tmp_path / "tune.json")
+    cfg = tune.tune(seqs, reset, reps=1, cache=cache)
+    assert not cfg["cached"] and len(cfg["timings"]) == len(tune.candidates(1))
+    again = tune.tune(seqs, reset, reps=1, cache=cache)
+    assert again["cached"] and again["item_px"] == cfg["item_px"]
+    reset()
+    batch = lib.Batch(seqs, blocks=cfg["blocks"])
+    batch.launch()
+    assert batch.status() == 0
+    for i, (wl, q) in enumerate(zip(wls, seqs)):
+        ref, _ = sequential(lib, wl)
+        for n in range(len(wl.frames)):
+            assert_same(batch_outputs(q, n), ref[n], f"tuned seq {i} frame {n}")
