@@ -419,24 +419,26 @@ def gaussian_irf_sigma(sigma: float, W: int, c: int) -> np.ndarray:
     return pmf / pmf.sum()
 
 
-def filter_loss(theta: np.ndarray, model: Model, frames, d_true: np.ndarray) -> float:
+def filter_loss(theta: np.ndarray, model: Model, frames, d_true: np.ndarray,
+                pi_in=None, faulty=None) -> float:
     """Mean over pixels and frames of (posterior mean - true depth)^2 for the
     filter run with theta = (beta, irf sigma, sigma_rw2, nu[0..8]). The
     posterior mean is the soft-argmax of the log pseudo-posterior at
-    temperature one bin."""
+    temperature one bin. ``pi_in`` and ``faulty`` are passed to ``run``
+    unchanged (inputs, not parameters)."""
     theta = np.asarray(theta, dtype=np.float64)
     mdl = Model(rows=model.rows, cols=model.cols, T=model.T, d_lo=model.d_lo,
                 D=model.D, d_min=model.d_min, d_max=model.d_max,
                 beta=float(theta[0]),
                 irf=gaussian_irf_sigma(float(theta[1]), model.W, model.c),
                 c=model.c, nu=theta[3:12].copy(), sigma_rw2=float(theta[2]))
-    _, outs = run(mdl, frames)
+    _, outs = run(mdl, frames, pi_in=pi_in, faulty=faulty)
     err = [(o["mean"] - np.asarray(d_true[n], np.float64)) ** 2 for n, o in enumerate(outs)]
     return float(np.mean(np.stack(err)))
 
 
 def filter_loss_grad_fd(theta: np.ndarray, model: Model, frames, d_true,
-                        rel_step: float = 1e-6) -> np.ndarray:
+                        rel_step: float = 1e-6, pi_in=None, faulty=None) -> np.ndarray:
     """Central finite differences of ``filter_loss`` with a relative step."""
     theta = np.asarray(theta, dtype=np.float64)
     g = np.zeros_like(theta)
@@ -445,6 +447,6 @@ def filter_loss_grad_fd(theta: np.ndarray, model: Model, frames, d_true,
         tp, tm = theta.copy(), theta.copy()
         tp[i] += h
         tm[i] -= h
-        g[i] = (filter_loss(tp, model, frames, d_true)
-                - filter_loss(tm, model, frames, d_true)) / (2 * h)
+        g[i] = (filter_loss(tp, model, frames, d_true, pi_in, faulty)
+                - filter_loss(tm, model, frames, d_true, pi_in, faulty)) / (2 * h)
     return g
