@@ -209,6 +209,54 @@ r3d_status r3d_batch_status(r3d_batch *batch, void *stream);
 /* Destroy a batch (synchronises the device first). NULL is ignored. */
 void r3d_batch_destroy(r3d_batch *batch);
 
+/* ---------------------------------------------------------------------------
+ * Differentiable filter.
+ *
+ * r3d_filter_forward runs Algorithm 1 over a sequence of photon-list frames
+ * and returns every frame's posterior mean and variance (the Gaussian state
+ * of eq. KL_div, Sec. III-A). r3d_filter_backward returns the gradient of a
+ * scalar loss J of those outputs, given dJ/dmean and dJ/dvar, with respect to
+ * the model parameters: beta (Sec. II-B), the IRF taps, sigma_rw2 and the 3x3
+ * weights nu (Sec. III-A, eq. predict). The posterior mean is the
+ * soft-argmax of the log pseudo-posterior at temperature one bin (Sec. II-C,
+ * eq. approx_post). Presence probabilities (pi_in) and faulty masks are
+ * inputs, not differentiated. The backward keeps only a checkpoint state
+ * every ckpt_every frames from the forward and recomputes the states inside
+ * each segment; the result does not depend on ckpt_every (bit-identical).
+ * Both calls are asynchronous on the stream and need the same workspace.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t nframes;               /* >= 1                                                  */
+    const int32_t *const *row_ptr; /* HOST array of nframes DEVICE pointers, int32[P+1]     */
+    const int16_t *const *toa;     /* HOST array of nframes DEVICE pointers                 */
+    const float *pi_in;            /* device [nframes*P] presence probabilities, or NULL    */
+    const uint8_t *faulty;         /* device [P] mask, or NULL                              */
+} r3d_frames;
+
+/* Device workspace bytes for a sequence of nframes with this checkpoint
+ * interval (R3D_EUNSUPPORTED when the model's T, D, W do not fit the
+ * adjoint kernel's LDS: about D + 0.53 T + 2 W <= 16000 words). */
+r3d_status r3d_grad_workspace_size(const r3d_ctx *ctx, int32_t nframes, int32_t ckpt_every,
+                                   size_t *bytes);
+
+/* Forward pass. init: the state before the first frame (device, read only).
+ * mean, var: device float[nframes*P], frame-major (the filter state after
+ * each frame). workspace: device, at least r3d_grad_workspace_size bytes,
+ * caller-owned; it holds the checkpoints until the backward call. */
+r3d_status r3d_filter_forward(r3d_ctx *ctx, const r3d_frames *frames, int32_t ckpt_every,
+                              const r3d_state *init, float *mean, float *var,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward pass, after r3d_filter_forward with the same context, frames,
+ * ckpt_every and workspace. grad_mean: device float[nframes*P] = dJ/dmean;
+ * grad_var: the same for var, or NULL (zero). grad: device double[11 + W],
+ * overwritten with dJ/dbeta, dJ/dsigma_rw2, dJ/dnu[0..8], dJ/dirf[0..W-1]
+ * (the tap gradient is 0 for a zero tap). */
+r3d_status r3d_filter_backward(r3d_ctx *ctx, const r3d_frames *frames, int32_t ckpt_every,
+                               const float *grad_mean, const float *grad_var,
+                               void *workspace, size_t workspace_bytes, double *grad,
+                               void *stream);
+
 /* Static description of a status code. */
 const char *r3d_status_string(r3d_status status);
 

@@ -10,6 +10,7 @@
 
 #include "r3d_internal.hpp"
 #include "r3d_tile.hpp"
+#include "r3d_adjoint.hpp"
 #include "r3d_batch.hpp"
 #include "r3d_pixel.hpp"
 
@@ -174,6 +175,7 @@ r3d_status r3d_create(const r3d_params* params, r3d_ctx** out) {
   m.D = params->D;
   m.W = W;
   m.c = params->c;
+  m.beta = (float)params->beta;
   m.scale2 = (float)((params->beta + 1.0) / params->beta * 1.4426950408889634);
   double hmax = 0.0;
   for (int j = 0; j < W; ++j) hmax = std::fmax(hmax, std::pow(c->irf[j], params->beta));
@@ -422,6 +424,185 @@ void r3d_batch_destroy(r3d_batch* b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   free_batch(b);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of the differentiable filter (offsets in bytes, 256-aligned).
+struct GradLayout {
+  int N = 0, E = 0, nseg = 0, npar = 0;
+  size_t P = 0, state_bytes = 0;
+  size_t ckpt = 0, seg = 0, am = 0, av = 0, cm = 0, cv = 0, pib = 0, bb = 0, part = 0;
+  size_t bytes = 0;
+  r3d::AdjGeom geo{};
+};
+
+bool grad_layout(const r3d::DevModel& M, int N, int E, GradLayout& L) {
+  L.geo = r3d::adjoint_geometry(M);
+  if (L.geo.waves == 0) return false;
+  L.N = N;
+  L.E = E;
+  L.nseg = (N + E - 1) / E;
+  L.P = (size_t)M.P;
+  L.npar = r3d::kThetaFixed + M.W;
+  L.state_bytes = 4 * L.P * sizeof(float);  // m, v, pi, b
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  L.ckpt = take(L.nseg * L.state_bytes);
+  L.seg = take((size_t)E * L.state_bytes);
+  L.am = take(2 * L.P * sizeof(float));
+  L.av = take(2 * L.P * sizeof(float));
+  L.cm = take(9 * L.P * sizeof(float));
+  L.cv = take(9 * L.P * sizeof(float));
+  L.pib = take(2 * L.P * sizeof(float));
+  L.bb = take(2 * L.P * sizeof(float));
+  L.part = take((size_t)L.geo.blocks * L.npar * sizeof(float));
+  L.bytes = off;
+  return true;
+}
+
+r3d_state state_at(char* base, size_t off, size_t P) {
+  float* f = reinterpret_cast<float*>(base + off);
+  return r3d_state{f, f + P, f + 2 * P, f + 3 * P};
+}
+
+hipError_t copy_state(const r3d_state& dst, const r3d_state& src, size_t P, hipStream_t s) {
+  const float* a[4] = {src.m, src.v, src.pi, src.b};
+  float* b[4] = {dst.m, dst.v, dst.pi, dst.b};
+  for (int i = 0; i < 4; ++i) {
+    const hipError_t e =
+        hipMemcpyAsync(b[i], a[i], P * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+r3d_status check_frames(const r3d_frames* f) {
+  if (!f || f->nframes < 1 || !f->row_ptr || !f->toa) return R3D_EINVAL;
+  for (int n = 0; n < f->nframes; ++n)
+    if (!f->row_ptr[n] || !f->toa[n]) return R3D_EINVAL;
+  return R3D_OK;
+}
+
+hipError_t forward_frame(const r3d::DevModel& M, const r3d_frames* f, int n, const r3d_state& prev,
+                         const r3d_state& next, hipStream_t s) {
+  const float* pin = f->pi_in ? f->pi_in + (size_t)n * M.P : nullptr;
+  r3d::StepIO io = make_io(pin, f->faulty, &prev, &next, nullptr);
+  io.row_ptr = f->row_ptr[n];
+  io.toa = f->toa[n];
+  return r3d::launch_step_plain(M, io, false, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+r3d_status r3d_grad_workspace_size(const r3d_ctx* ctx, int32_t nframes, int32_t ckpt_every,
+                                   size_t* bytes) {
+  if (!ctx || !bytes || nframes < 1 || ckpt_every < 1) return R3D_EINVAL;
+  GradLayout L;
+  if (!grad_layout(ctx->dm, nframes, ckpt_every, L)) return R3D_EUNSUPPORTED;
+  *bytes = L.bytes;
+  return R3D_OK;
+}
+
+r3d_status r3d_filter_forward(r3d_ctx* ctx, const r3d_frames* frames, int32_t ckpt_every,
+                              const r3d_state* init, float* mean, float* var, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  if (!ctx || !mean || !var || !workspace || ckpt_every < 1) return R3D_EINVAL;
+  if (check_frames(frames) != R3D_OK || check_state(init) != R3D_OK) return R3D_EINVAL;
+  const r3d::DevModel& M = ctx->dm;
+  GradLayout L;
+  if (!grad_layout(M, frames->nframes, ckpt_every, L)) return R3D_EUNSUPPORTED;
+  if (workspace_bytes < L.bytes) return R3D_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = static_cast<char*>(workspace);
+  float* pib = reinterpret_cast<float*>(base + L.pib);
+  float* bb = reinterpret_cast<float*>(base + L.bb);
+  r3d_state prev = *init;
+  hipError_t e = hipSuccess;
+  for (int n = 0; n < L.N && e == hipSuccess; ++n) {
+    if (n % L.E == 0) e = copy_state(state_at(base, L.ckpt + (n / L.E) * L.state_bytes, L.P), prev,
+                                     L.P, s);
+    const r3d_state next{mean + (size_t)n * L.P, var + (size_t)n * L.P, pib + (n & 1) * L.P,
+                         bb + (n & 1) * L.P};
+    if (e == hipSuccess) e = forward_frame(M, frames, n, prev, next, s);
+    prev = next;
+  }
+  return hip_status(e);
+}
+
+r3d_status r3d_filter_backward(r3d_ctx* ctx, const r3d_frames* frames, int32_t ckpt_every,
+                               const float* grad_mean, const float* grad_var, void* workspace,
+                               size_t workspace_bytes, double* grad, void* stream) {
+  if (!ctx || !grad_mean || !grad || !workspace || ckpt_every < 1) return R3D_EINVAL;
+  if (check_frames(frames) != R3D_OK) return R3D_EINVAL;
+  const r3d::DevModel& M = ctx->dm;
+  GradLayout L;
+  if (!grad_layout(M, frames->nframes, ckpt_every, L)) return R3D_EUNSUPPORTED;
+  if (workspace_bytes < L.bytes) return R3D_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = static_cast<char*>(workspace);
+  const size_t P = L.P;
+  float* am[2] = {reinterpret_cast<float*>(base + L.am), reinterpret_cast<float*>(base + L.am) + P};
+  float* av[2] = {reinterpret_cast<float*>(base + L.av), reinterpret_cast<float*>(base + L.av) + P};
+  float* cm = reinterpret_cast<float*>(base + L.cm);
+  float* cv = reinterpret_cast<float*>(base + L.cv);
+  float* part = reinterpret_cast<float*>(base + L.part);
+  const int N = L.N;
+
+  hipError_t e = r3d::launch_fill_f64(grad, (size_t)L.npar, 0.0, s);
+  int cur = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(am[cur], grad_mean + (size_t)(N - 1) * P, P * sizeof(float),
+                       hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = grad_var ? hipMemcpyAsync(av[cur], grad_var + (size_t)(N - 1) * P, P * sizeof(float),
+                                  hipMemcpyDeviceToDevice, s)
+                 : r3d::launch_fill_f32(av[cur], P, 0.f, s);
+  for (int sg = L.nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
+    const int f0 = sg * L.E;
+    const int f1 = std::min(N, f0 + L.E);
+    const r3d_state ck = state_at(base, L.ckpt + sg * L.state_bytes, P);
+    // recompute the states after frames f0 .. f1-2 of the segment
+    r3d_state prev = ck;
+    for (int n = f0; n + 1 < f1 && e == hipSuccess; ++n) {
+      const r3d_state next = state_at(base, L.seg + (n - f0) * L.state_bytes, P);
+      e = forward_frame(M, frames, n, prev, next, s);
+      prev = next;
+    }
+    for (int n = f1 - 1; n >= f0 && e == hipSuccess; --n) {
+      const r3d_state before =
+          n == f0 ? ck : state_at(base, L.seg + (n - 1 - f0) * L.state_bytes, P);
+      r3d::AdjIO io{};
+      io.row_ptr = frames->row_ptr[n];
+      io.toa = frames->toa[n];
+      io.faulty = frames->faulty;
+      io.pm = before.m;
+      io.pv = before.v;
+      io.ppi = before.pi;
+      io.gm = am[cur];
+      io.gv = av[cur];
+      io.cm = cm;
+      io.cv = cv;
+      io.part = part;
+      e = r3d::launch_adjoint(M, io, L.geo, s);
+      if (e == hipSuccess) e = r3d::launch_theta_reduce(M, part, L.geo.blocks, grad, s);
+      if (e == hipSuccess && n > 0) {
+        e = r3d::launch_adjoint_gather(M, cm, cv, grad_mean + (size_t)(n - 1) * P,
+                                       grad_var ? grad_var + (size_t)(n - 1) * P : nullptr,
+                                       am[cur ^ 1], av[cur ^ 1], s);
+        cur ^= 1;
+      }
+    }
+  }
+  return hip_status(e);
 }
 
 r3d_status r3d_last_device_status(r3d_ctx* ctx, void* stream) {

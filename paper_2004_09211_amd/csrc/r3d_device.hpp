@@ -89,11 +89,20 @@ __device__ __forceinline__ void merge_components(Comps& C) {
   for (int k = 0; k < 9; ++k) C.live |= (C.w2[k] > -INFINITY ? 1u : 0u) << k;
 }
 
-__device__ __forceinline__ void build_components(const DevModel& M, const float* __restrict__ pm,
-                                                 const float* __restrict__ pv,
-                                                 const float* __restrict__ ppi, int p, Comps& C) {
+// The 9 prior components of pixel p before merging (Sec. III-A, eq.
+// predict): a detected in-frame neighbour contributes its state N(m, v), any
+// other position the flat Gaussian; the random walk adds sigma_rw2. Also
+// returns each variance V[k] and the mask of positions that read a
+// neighbour's state (detected and in frame).
+__device__ __forceinline__ void build_components_raw(const DevModel& M,
+                                                     const float* __restrict__ pm,
+                                                     const float* __restrict__ pv,
+                                                     const float* __restrict__ ppi, int p,
+                                                     Comps& C, float (&Vk)[9], unsigned& nb) {
   const int r = p / M.cols;
   const int col = p - r * M.cols;
+  nb = 0u;
+  C.live = 0u;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const int rr = r + k / 3 - 1, cc = col + k % 3 - 1;
@@ -103,13 +112,24 @@ __device__ __forceinline__ void build_components(const DevModel& M, const float*
       if (ppi[q] > 0.5f) {
         m = pm[q];
         v = pv[q];
+        nb |= 1u << k;
       }
     }
     const float V = v + M.sigma_rw2;
+    Vk[k] = V;
     C.m[k] = m;
     C.k2[k] = 0.5f * kLog2e / V;
     C.w2[k] = M.lognu2[k] - 0.5f * (kLog2TwoPi + log2f(V));
+    C.live |= (C.w2[k] > -INFINITY ? 1u : 0u) << k;
   }
+}
+
+__device__ __forceinline__ void build_components(const DevModel& M, const float* __restrict__ pm,
+                                                 const float* __restrict__ pv,
+                                                 const float* __restrict__ ppi, int p, Comps& C) {
+  float Vk[9];
+  unsigned nb;
+  build_components_raw(M, pm, pv, ppi, p, C, Vk, nb);
   merge_components(C);
 }
 

@@ -21,6 +21,7 @@ enum : unsigned { kErrRange = 1u, kErrOverflow = 2u, kErrTimeout = 4u };
 // Log-quantities are in base 2 (the hardware exp/log are base 2).
 struct DevModel {
   int rows, cols, P, T, d_lo, D, W, c;
+  float beta;        // beta-divergence parameter
   float scale2;      // (beta+1)/beta * log2(e): cost in log2 units
   float hmax;        // an upper bound of max_j irf^beta[j] (for the culling bound)
   float m_flat;      // (d_min+d_max)/2

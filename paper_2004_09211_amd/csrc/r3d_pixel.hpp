@@ -46,6 +46,169 @@ __device__ __forceinline__ float packed_count(const unsigned* hist, int t) {
   return (float)((hist[t >> 1] >> ((t & 1) << 4)) & 0xffffu);
 }
 
+// Candidate depth range [dlo_c, dhi_c] of a pixel (empty when dlo_c > dhi_c)
+// from the bound above, and per component the radius R around its mean
+// inside which its log2-density reaches theta, and the wider radius Rl
+// (theta - kPixLiveGap) of the components kept in a chunk's mixture.
+__device__ __forceinline__ void candidate_range(const DevModel& M, const Comps& C, unsigned live,
+                                                float K, bool faulty, int lane, float (&R)[9],
+                                                float (&Rl)[9], int& dlo_c, int& dhi_c) {
+  const int dhi = M.d_lo + M.D - 1;
+  const float l2max_ub = faulty ? 0.f : M.scale2 * M.hmax * K;
+  float Llb = -INFINITY;
+  if (lane < 9 && ((live >> lane) & 1u)) {
+    float mk = C.m[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) mk = lane == k ? C.m[k] : mk;
+    const float dk = fminf(fmaxf(rintf(mk), (float)M.d_lo), (float)dhi);
+    Llb = log_prior2(C, dk, live);
+  }
+  Llb = group_max<1, 32>(Llb);
+  const float theta = Llb - kPixCullMargin2 - l2max_ub - kPixLog2Nine;
+  float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    R[k] = C.w2[k] >= theta ? sqrtf((C.w2[k] - theta) / C.k2[k]) + 2.0f : -1e30f;
+    Rl[k] = C.w2[k] >= theta - kPixLiveGap ? sqrtf((C.w2[k] - theta + kPixLiveGap) / C.k2[k]) + 2.0f
+                                           : -1e30f;
+    if (R[k] > 0.f) {
+      lo = fminf(lo, C.m[k] - R[k]);
+      hi = fmaxf(hi, C.m[k] + R[k]);
+    }
+  }
+  dlo_c = M.d_lo;
+  dhi_c = M.d_lo - 1;  // empty unless some component reaches theta
+  if (lo <= hi) {
+    dlo_c = (int)fmaxf(floorf(lo), (float)M.d_lo);
+    dhi_c = (int)fminf(ceilf(hi), (float)dhi);
+  }
+}
+
+// Wave-uniform masks of the 64-depth chunk starting at d0: ``cand`` the
+// components that reach theta somewhere in it (zero: the chunk has no
+// weight), ``cmask`` the components kept in its mixture.
+__device__ __forceinline__ void chunk_masks(const Comps& C, const float (&R)[9],
+                                            const float (&Rl)[9], int d0, unsigned& cand,
+                                            unsigned& cmask) {
+  const float dc = (float)d0 + 31.5f;
+  cand = 0u;
+  cmask = 0u;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    cand |= (fabsf(dc - C.m[k]) <= R[k] + 32.0f ? 1u : 0u) << k;
+    cmask |= (fabsf(dc - C.m[k]) <= Rl[k] + 32.0f ? 1u : 0u) << k;
+  }
+  cand = __builtin_amdgcn_readfirstlane(cand);
+  cmask = __builtin_amdgcn_readfirstlane(cmask);
+}
+
+// Cost gather at depth d: sum over taps j of tap[j] * z[d - c + j] in
+// increasing j (bins outside [0, T) count zero). ``sparse`` walks only the
+// non-empty bins of the window; both forms give the same bits.
+__device__ __forceinline__ float cost_gather(const DevModel& M, const unsigned* hist,
+                                             const unsigned* nzmask, const float* tap, int d,
+                                             bool sparse) {
+  float ell = 0.f;
+  const int t0 = d - M.c;
+  if (sparse) {
+    const int lo = t0 > 0 ? t0 : 0;
+    const int hi = (t0 + M.W) < M.T ? (t0 + M.W) : M.T;
+    for (int t = lo; t < hi;) {
+      const int base = t & ~31;
+      unsigned bits = nzmask[base >> 5] & (~0u << (t - base));
+      if (hi - base < 32) bits &= (1u << (hi - base)) - 1u;
+      while (bits) {
+        const int tb = base + __builtin_ctz(bits);
+        bits &= bits - 1u;
+        ell = fmaf(tap[tb - t0], packed_count(hist, tb), ell);
+      }
+      t = base + 32;
+    }
+  } else {
+    const int jlo = t0 < 0 ? -t0 : 0;
+    const int jhi = (M.T - t0) < M.W ? (M.T - t0) : M.W;
+    for (int j = jlo; j < jhi; ++j) ell = fmaf(tap[j], packed_count(hist, t0 + j), ell);
+  }
+  return ell;
+}
+
+// Online centred moments of the weights exp2(L2 - Rm) at depths d: a new
+// maximum rescales the sums and re-centres them on its depth.
+__device__ __forceinline__ void moment_push(float L2, float d, float& Rm, float& ref, float& S0,
+                                            float& S1, float& S2) {
+  if (L2 > Rm) {
+    const float sc = fast_exp2(Rm - L2);
+    const float delta = ref - d;
+    S0 *= sc;
+    S1 *= sc;
+    S2 *= sc;
+    S2 = fmaf(delta, fmaf(2.f, S1, delta * S0), S2);
+    S1 = fmaf(delta, S0, S1);
+    Rm = L2;
+    ref = d;
+  }
+  if (L2 > -INFINITY) {
+    const float w = fast_exp2(L2 - Rm);
+    const float e = d - ref;
+    S0 += w;
+    S1 = fmaf(e, w, S1);
+    S2 = fmaf(e * e, w, S2);
+  }
+}
+
+// Merge the lanes' moments: larger maximum wins (lower depth on ties); the
+// other's sums are rescaled and re-centred on the winner (symmetric, so every
+// lane ends with the same bits).
+__device__ __forceinline__ void moment_merge_lanes(float& Rm, float& ref, float& S0, float& S1,
+                                                   float& S2) {
+#pragma unroll
+  for (int xm = 1; xm <= 32; xm <<= 1) {
+    const float oR = __shfl_xor(Rm, xm), oref = __shfl_xor(ref, xm);
+    const float o0 = __shfl_xor(S0, xm), o1 = __shfl_xor(S1, xm), o2 = __shfl_xor(S2, xm);
+    const bool other = (oR > Rm) || (oR == Rm && oref < ref);
+    const float wR = other ? oR : Rm, wref = other ? oref : ref;
+    auto bring = [&](float r, float rf, float& s0, float& s1, float& s2)
+        __attribute__((always_inline)) {
+      const float sc = (r == -INFINITY) ? 0.f : fast_exp2(r - wR);
+      s0 *= sc;
+      s1 *= sc;
+      s2 *= sc;
+      const float delta = rf - wref;
+      s2 = fmaf(delta, fmaf(2.f, s1, delta * s0), s2);
+      s1 = fmaf(delta, s0, s1);
+    };
+    float a0 = S0, a1 = S1, a2 = S2, b0 = o0, b1 = o1, b2 = o2;
+    bring(Rm, ref, a0, a1, a2);
+    bring(oR, oref, b0, b1, b2);
+    S0 = a0 + b0;
+    S1 = a1 + b1;
+    S2 = a2 + b2;
+    Rm = wR;
+    ref = wref;
+  }
+}
+
+// Photon-list histogram of pixel p into the zeroed LDS region (packed
+// counts and non-empty-bin mask); returns the photon count and ORs error
+// bits into ``bad``.
+__device__ __forceinline__ float csr_histogram(const DevModel& M, const int32_t* row_ptr,
+                                               const int16_t* toa, int p, int lane,
+                                               unsigned* hist, unsigned* nzmask, unsigned& bad) {
+  const int b = row_ptr[p], e = row_ptr[p + 1];
+  if (e < b) bad |= kErrRange;
+  if (e - b > 65535) bad |= kErrOverflow;  // 16-bit bins could overflow
+  for (int k = b + lane; k < e; k += 64) {
+    const int t = toa[k];
+    if ((unsigned)t < (unsigned)M.T) {
+      atomicAdd(&hist[t >> 1], 1u << ((t & 1) << 4));
+      atomicOr(&nzmask[t >> 5], 1u << (t & 31));
+    } else {
+      bad |= kErrRange;
+    }
+  }
+  return (float)(e > b ? e - b : 0);
+}
+
 // Per-pixel step. ``hist`` is this wavefront's 16-byte aligned LDS region of
 // pixel_lds_words(T) words; ``sh_h`` and ``sh_irf`` hold irf^beta and irf
 // (W floats each).
@@ -88,18 +251,7 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
       }
       K = group_sum<1, 32>(ks);
     } else {
-      const int b = io.row_ptr[p], e = io.row_ptr[p + 1];
-      if (e < b) bad |= kErrRange;
-      if (e - b > 65535) bad |= kErrOverflow;  // 16-bit bins could overflow
-      for (int k = b + lane; k < e; k += 64) {
-        const int t = io.toa[k];
-        if ((unsigned)t < (unsigned)M.T) {
-          atomicAdd(&hist[t >> 1], 1u << ((t & 1) << 4));
-          atomicOr(&nzmask[t >> 5], 1u << (t & 31));
-        } else
-          bad |= kErrRange;
-      }
-      K = (float)(e > b ? e - b : 0);
+      K = csr_histogram(M, io.row_ptr, io.toa, p, lane, hist, nzmask, bad);
     }
   }
   if (bad) atomicOr(M.err, bad);
@@ -109,124 +261,26 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
   Comps C;
   build_components(M, io.pm, io.pv, io.ppi, p, C);
   const unsigned live = __builtin_amdgcn_readfirstlane(C.live);
-  const int dhi = M.d_lo + M.D - 1;
 
   // ---- candidate depth range from the bound ----
-  const float l2max_ub = faulty ? 0.f : M.scale2 * M.hmax * K;
-  float Llb = -INFINITY;
-  if (lane < 9 && ((live >> lane) & 1u)) {
-    float mk = C.m[0];
-#pragma unroll
-    for (int k = 1; k < 9; ++k) mk = lane == k ? C.m[k] : mk;
-    const float dk = fminf(fmaxf(rintf(mk), (float)M.d_lo), (float)dhi);
-    Llb = log_prior2(C, dk, live);
-  }
-  Llb = group_max<1, 32>(Llb);
-  const float theta = Llb - kPixCullMargin2 - l2max_ub - kPixLog2Nine;
   float R[9], Rl[9];
-  float lo = INFINITY, hi = -INFINITY;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    R[k] = C.w2[k] >= theta ? sqrtf((C.w2[k] - theta) / C.k2[k]) + 2.0f : -1e30f;
-    Rl[k] = C.w2[k] >= theta - kPixLiveGap ? sqrtf((C.w2[k] - theta + kPixLiveGap) / C.k2[k]) + 2.0f
-                                           : -1e30f;
-    if (R[k] > 0.f) {
-      lo = fminf(lo, C.m[k] - R[k]);
-      hi = fmaxf(hi, C.m[k] + R[k]);
-    }
-  }
-  int dlo_c = M.d_lo, dhi_c = M.d_lo - 1;  // empty unless some component reaches theta
-  if (lo <= hi) {
-    dlo_c = (int)fmaxf(floorf(lo), (float)M.d_lo);
-    dhi_c = (int)fminf(ceilf(hi), (float)dhi);
-  }
+  int dlo_c, dhi_c;
+  candidate_range(M, C, live, K, faulty, lane, R, Rl, dlo_c, dhi_c);
 
   // ---- a3 + a5 on the candidates: online centred moments per lane ----
   const bool sparse = !kHist && 3.f * K <= (float)M.T;  // wave-uniform
   float Rm = -INFINITY, S0 = 0.f, S1 = 0.f, S2 = 0.f, ref = 0.f;
   for (int d0 = dlo_c; d0 <= dhi_c; d0 += 64) {
-    const float dc = (float)d0 + 31.5f;
-    unsigned cand = 0u, cmask = 0u;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      cand |= (fabsf(dc - C.m[k]) <= R[k] + 32.0f ? 1u : 0u) << k;
-      cmask |= (fabsf(dc - C.m[k]) <= Rl[k] + 32.0f ? 1u : 0u) << k;
-    }
-    if (__builtin_amdgcn_readfirstlane(cand) == 0u) continue;
-    cmask = __builtin_amdgcn_readfirstlane(cmask);
+    unsigned cand, cmask;
+    chunk_masks(C, R, Rl, d0, cand, cmask);
+    if (cand == 0u) continue;
     const int d = d0 + lane;
     if (d > dhi_c) continue;
-    float ell = 0.f;
-    if (!faulty) {
-      const int t0 = d - M.c;
-      if (sparse) {
-        const int lo = t0 > 0 ? t0 : 0;
-        const int hi = (t0 + M.W) < M.T ? (t0 + M.W) : M.T;
-        for (int t = lo; t < hi;) {
-          const int base = t & ~31;
-          unsigned bits = nzmask[base >> 5] & (~0u << (t - base));
-          if (hi - base < 32) bits &= (1u << (hi - base)) - 1u;
-          while (bits) {
-            const int tb = base + __builtin_ctz(bits);
-            bits &= bits - 1u;
-            ell = fmaf(sh_h[tb - t0], packed_count(hist, tb), ell);
-          }
-          t = base + 32;
-        }
-      } else {
-        const int jlo = t0 < 0 ? -t0 : 0;
-        const int jhi = (M.T - t0) < M.W ? (M.T - t0) : M.W;
-        for (int j = jlo; j < jhi; ++j) ell = fmaf(sh_h[j], packed_count(hist, t0 + j), ell);
-      }
-    }
+    const float ell = faulty ? 0.f : cost_gather(M, hist, nzmask, sh_h, d, sparse);
     const float L2 = fmaf(ell, M.scale2, log_prior2(C, (float)d, cmask));
-    if (L2 > Rm) {
-      const float sc = fast_exp2(Rm - L2);
-      const float delta = ref - (float)d;
-      S0 *= sc;
-      S1 *= sc;
-      S2 *= sc;
-      S2 = fmaf(delta, fmaf(2.f, S1, delta * S0), S2);
-      S1 = fmaf(delta, S0, S1);
-      Rm = L2;
-      ref = (float)d;
-    }
-    if (L2 > -INFINITY) {
-      const float w = fast_exp2(L2 - Rm);
-      const float e = (float)d - ref;
-      S0 += w;
-      S1 = fmaf(e, w, S1);
-      S2 = fmaf(e * e, w, S2);
-    }
+    moment_push(L2, (float)d, Rm, ref, S0, S1, S2);
   }
-  // merge the lanes: larger maximum wins (lower depth on ties); the other's
-  // sums are rescaled and re-centred on the winner (symmetric, so every lane
-  // ends with the same bits)
-#pragma unroll
-  for (int xm = 1; xm <= 32; xm <<= 1) {
-    const float oR = __shfl_xor(Rm, xm), oref = __shfl_xor(ref, xm);
-    const float o0 = __shfl_xor(S0, xm), o1 = __shfl_xor(S1, xm), o2 = __shfl_xor(S2, xm);
-    const bool other = (oR > Rm) || (oR == Rm && oref < ref);
-    const float wR = other ? oR : Rm, wref = other ? oref : ref;
-    auto bring = [&](float r, float rf, float& s0, float& s1, float& s2)
-        __attribute__((always_inline)) {
-      const float sc = (r == -INFINITY) ? 0.f : fast_exp2(r - wR);
-      s0 *= sc;
-      s1 *= sc;
-      s2 *= sc;
-      const float delta = rf - wref;
-      s2 = fmaf(delta, fmaf(2.f, s1, delta * s0), s2);
-      s1 = fmaf(delta, s0, s1);
-    };
-    float a0 = S0, a1 = S1, a2 = S2, b0 = o0, b1 = o1, b2 = o2;
-    bring(Rm, ref, a0, a1, a2);
-    bring(oR, oref, b0, b1, b2);
-    S0 = a0 + b0;
-    S1 = a1 + b1;
-    S2 = a2 + b2;
-    Rm = wR;
-    ref = wref;
-  }
+  moment_merge_lanes(Rm, ref, S0, S1, S2);
   const float mu = S1 / S0;
   const int dstar = (int)ref;
   const float mean = ref + mu;

@@ -50,6 +50,11 @@ class CSequence(ctypes.Structure):
                 ("pi_in", c_void_p), ("faulty", c_void_p), ("chunk_rows", c_int32)]
 
 
+class CFrames(ctypes.Structure):
+    _fields_ = [("nframes", c_int32), ("row_ptr", POINTER(c_void_p)), ("toa", POINTER(c_void_p)),
+                ("pi_in", c_void_p), ("faulty", c_void_p)]
+
+
 class CBatchOptions(ctypes.Structure):
     _fields_ = [("spin_limit", ctypes.c_uint32), ("blocks", c_int32)]
 
@@ -71,6 +76,11 @@ SIGNATURES = {
     "r3d_batch_launch": (c_int32, [c_void_p, c_void_p]),
     "r3d_batch_status": (c_int32, [c_void_p, c_void_p]),
     "r3d_batch_destroy": (None, [c_void_p]),
+    "r3d_grad_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, POINTER(ctypes.c_size_t)]),
+    "r3d_filter_forward": (c_int32, [c_void_p, POINTER(CFrames), c_int32, POINTER(CState),
+                                     c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
+    "r3d_filter_backward": (c_int32, [c_void_p, POINTER(CFrames), c_int32, c_void_p, c_void_p,
+                                      c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),
     "r3d_status_string": (c_char_p, [c_int32]),
 }
 
@@ -242,6 +252,48 @@ class Context:
 
     def last_device_status(self, stream=None) -> int:
         return int(_lib.r3d_last_device_status(self._h, _stream(stream)))
+
+    def grad_workspace_size(self, nframes: int, ckpt_every: int) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.r3d_grad_workspace_size(self._h, int(nframes), int(ckpt_every), byref(n)),
+               "r3d_grad_workspace_size")
+        return int(n.value)
+
+    def filter_forward(self, frames: "Frames", ckpt_every: int, init: State, mean, var,
+                       workspace, stream=None):
+        ci = init.c()
+        _check(_lib.r3d_filter_forward(self._h, byref(frames.c), int(ckpt_every), byref(ci),
+                                       _ptr(mean, torch.float32), _ptr(var, torch.float32),
+                                       _ptr(workspace, torch.uint8), workspace.numel(),
+                                       _stream(stream)), "r3d_filter_forward")
+
+    def filter_backward(self, frames: "Frames", ckpt_every: int, grad_mean, grad_var, workspace,
+                        grad, stream=None):
+        _check(_lib.r3d_filter_backward(self._h, byref(frames.c), int(ckpt_every),
+                                        _ptr(grad_mean, torch.float32),
+                                        _ptr(grad_var, torch.float32),
+                                        _ptr(workspace, torch.uint8), workspace.numel(),
+                                        _ptr(grad, torch.float64), _stream(stream)),
+               "r3d_filter_backward")
+
+
+class Frames:
+    """A sequence of photon-list frames (device (row_ptr, toa) pairs) with
+    optional presence probabilities [nframes * P] and faulty mask [P]."""
+
+    def __init__(self, frames, pi_in: Optional[torch.Tensor] = None,
+                 faulty: Optional[torch.Tensor] = None):
+        self.frames = list(frames)
+        n = len(self.frames)
+        self._rp = (c_void_p * n)(*[_ptr(f[0], torch.int32) for f in self.frames])
+        self._toa = (c_void_p * n)(*[_ptr(f[1], torch.int16) for f in self.frames])
+        self.pi_in, self.faulty = pi_in, faulty
+        self.c = CFrames(n, ctypes.cast(self._rp, POINTER(c_void_p)),
+                         ctypes.cast(self._toa, POINTER(c_void_p)),
+                         _ptr(pi_in, torch.float32), _ptr(faulty, torch.uint8))
+
+    def __len__(self):
+        return len(self.frames)
 
 
 class R3DFilter:

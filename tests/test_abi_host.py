@@ -138,6 +138,39 @@ def test_batch_entry_points_reject_bad_arguments(r3d):
     lib.r3d_batch_destroy(None)
 
 
+def test_filter_entry_points_reject_bad_arguments(r3d):
+    lib = r3d.load()
+    n = ctypes.c_size_t()
+    assert lib.r3d_grad_workspace_size(None, 5, 5, ctypes.byref(n)) == -1
+    fr = r3d.CFrames()
+    st = r3d.CState()
+    assert lib.r3d_filter_forward(None, ctypes.byref(fr), 5, ctypes.byref(st), None, None, None,
+                                  0, None) == -1
+    assert lib.r3d_filter_backward(None, ctypes.byref(fr), 5, None, None, None, 0, None,
+                                   None) == -1
+
+
+def test_frames_layout_matches_c(tmp_path, r3d):
+    src = tmp_path / "fr.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "r3d.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(r3d_frames), offsetof(r3d_frames, row_ptr),
+         offsetof(r3d_frames, toa), offsetof(r3d_frames, pi_in), offsetof(r3d_frames, faulty));
+  return 0;
+}
+""")
+    exe = tmp_path / "fr"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    F = r3d.CFrames
+    assert got == [ctypes.sizeof(F), F.row_ptr.offset, F.toa.offset, F.pi_in.offset,
+                   F.faulty.offset]
+
+
 def test_sequence_layout_matches_c(tmp_path, r3d):
     src = tmp_path / "seq.c"
     src.write_text("""
