@@ -199,6 +199,50 @@ def run_batched(args):
                          "log-normal photon counts, fp32 photon lists)")
 
 
+def run_grad(args):
+    """Differentiable filter on 128x128 x 20 frames (T=1024, moving plane):
+    forward with a checkpoint every 5 frames, then the adjoint of
+    loss = mean (posterior mean - true depth)^2, timed separately (median of
+    the repetitions) with events on the launch stream."""
+    import torch
+    import synth
+    from paper_2004_09211_amd import r3d
+
+    dev = torch.device("cuda:0")
+    wl = synth.config5(seed=0, device=dev)
+    frames = r3d.Frames([(f.row_ptr, f.toa) for f in wl.frames])
+    ctx = r3d.Context(wl.params())
+    N, P, E = len(wl.frames), wl.P, 5
+    init = r3d.State.empty(P, dev)
+    ctx.state_init(init)
+    ws = torch.empty(ctx.grad_workspace_size(N, E), dtype=torch.uint8, device=dev)
+    mean = torch.empty(N * P, device=dev)
+    var = torch.empty(N * P, device=dev)
+    grad = torch.empty(11 + wl.W, dtype=torch.float64, device=dev)
+    truth = wl.depth_true.reshape(-1).float()
+    fw, bw = [], []
+    for i in range(args.grad_reps + 1):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        ctx.filter_forward(frames, E, init, mean, var, ws)
+        e[1].record()
+        gm = (2.0 / (N * P)) * (mean - truth)
+        ctx.filter_backward(frames, E, gm, None, ws, grad)
+        e[2].record()
+        torch.cuda.synchronize()
+        if i > 0:
+            fw.append(e[0].elapsed_time(e[1]))
+            bw.append(e[1].elapsed_time(e[2]))
+    if ctx.last_device_status() != 0:
+        raise RuntimeError("gradient pass reported a device error")
+    fms, bms = sorted(fw)[len(fw) // 2], sorted(bw)[len(bw) // 2]
+    return dict(value=round(N * P / ((fms + bms) * 1e-3), 1), unit="pixel-frames/s",
+                forward_ms=round(fms, 3), backward_ms=round(bms, 3),
+                backward_over_forward=round(bms / fms, 2), ckpt_every=E,
+                workload="128x128 x 20 frames, T=1024, photon lists; gradient w.r.t. beta, "
+                         "IRF taps, sigma_rw2, nu[9]")
+
+
 def cpu_baseline(params, sample_hist, rows):
     import numpy as np
     import oracle
@@ -229,6 +273,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--tune-cache", default="")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--grad-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is measured on a single MI355X "
@@ -238,6 +284,7 @@ def main():
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     res, sample = run_gpu(args)
     batched = None if args.no_batched else run_batched(args)
+    gradient = None if args.no_grad else run_grad(args)
     cpu = cpu_baseline(res["params"], sample, args.cpu_rows) if sample is not None else None
     line = dict(
         metric=METRIC, value=round(res["value"], 1), unit="pixel-frames/s", n_gpus=1,
@@ -253,7 +300,7 @@ def main():
                     dict(value=round(res["plain"]["value"], 1),
                          ms_per_step=round(res["plain"]["ms_per_step"], 3),
                          speedup=round(res["value"] / res["plain"]["value"], 3))),
-        roofline=res["roofline"], cpu_baseline=cpu, batched=batched)
+        roofline=res["roofline"], cpu_baseline=cpu, batched=batched, gradient=gradient)
     print(json.dumps(line), flush=True)
 
 
