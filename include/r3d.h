@@ -149,6 +149,26 @@ r3d_status r3d_step_hist(r3d_ctx *ctx, const uint16_t *hist,
                          const r3d_state *prev, const r3d_state *next,
                          const r3d_out *out, void *stream);
 
+/* Consecutive frames of fp16 histograms through Algorithm 1 (Sec. III-B),
+ * each frame exactly as r3d_step_hist computes it (bit-identical results),
+ * with the work of neighbouring frames overlapped: the cost of a frame is
+ * bounded (its maximum over the depth grid, which needs no filter state) in
+ * the same launch that resolves the previous frame's pseudo-posterior.
+ * hist: HOST array of nframes DEVICE pointers, each fp16 [P][T] as for
+ * r3d_step_hist and 16-byte aligned (else R3D_EUNSUPPORTED). Frame n reads
+ * state[n % 2] and writes state[(n + 1) % 2]; state[0] holds the state before
+ * the first frame; the two states must not alias. pi_in: device
+ * [nframes * P], frame-major, or NULL (every pixel detected). faulty: device
+ * [P] mask applied to every frame, or NULL. out: device arrays of
+ * nframes * P elements, frame-major; any pointer may be NULL.
+ * R3D_EUNSUPPORTED when T is not a multiple of 8 or the IRF is too long for
+ * the tile kernels (r3d_step_hist then still runs R3D_FP32 contexts).
+ * Asynchronous; uses the context's bound buffers, so a context runs one
+ * step or sequence at a time. */
+r3d_status r3d_run_hist(r3d_ctx *ctx, const uint16_t *const *hist, int32_t nframes,
+                        const float *pi_in, const uint8_t *faulty, const r3d_state *state,
+                        const r3d_out *out, void *stream);
+
 /* Synchronise the stream, then read and clear the device error word:
  * R3D_OK, R3D_ERANGE or R3D_EOVERFLOW (the first kind recorded). */
 r3d_status r3d_last_device_status(r3d_ctx *ctx, void *stream);

@@ -70,6 +70,8 @@ SIGNATURES = {
                                POINTER(CState), POINTER(CState), POINTER(COut), c_void_p]),
     "r3d_step_hist": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                 POINTER(CState), POINTER(CState), POINTER(COut), c_void_p]),
+    "r3d_run_hist": (c_int32, [c_void_p, POINTER(c_void_p), c_int32, c_void_p, c_void_p,
+                               POINTER(CState), POINTER(COut), c_void_p]),
     "r3d_last_device_status": (c_int32, [c_void_p, c_void_p]),
     "r3d_batch_create": (c_int32, [POINTER(CSequence), c_int32, POINTER(CBatchOptions),
                                    POINTER(c_void_p)]),
@@ -249,6 +251,18 @@ class Context:
         _check(_lib.r3d_step_hist(self._h, _ptr(hist, torch.float16),
                                   _ptr(pi_in, torch.float32), _ptr(faulty, torch.uint8),
                                   byref(cp), byref(cn), byref(co), _stream(stream)), "r3d_step_hist")
+
+    def run_hist(self, hists, states, out: Outputs, pi_in=None, faulty=None, stream=None):
+        """Frames ``hists`` (fp16 [P, T] device tensors) through the filter:
+        frame n reads ``states[n % 2]`` and writes ``states[(n + 1) % 2]``;
+        ``out`` holds ``len(hists) * P`` elements per output, frame-major."""
+        n = len(hists)
+        hp = (c_void_p * n)(*[_ptr(h, torch.float16) for h in hists])
+        cs = (CState * 2)(states[0].c(), states[1].c())
+        co = out.c()
+        _check(_lib.r3d_run_hist(self._h, ctypes.cast(hp, POINTER(c_void_p)), n,
+                                 _ptr(pi_in, torch.float32), _ptr(faulty, torch.uint8),
+                                 cs, byref(co), _stream(stream)), "r3d_run_hist")
 
     def last_device_status(self, stream=None) -> int:
         return int(_lib.r3d_last_device_status(self._h, _stream(stream)))

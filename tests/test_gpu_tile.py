@@ -177,3 +177,61 @@ def test_full_size_sampled(lib, prec):
     ref = light_cone_oracle(model, frames, targets, wl.nframes - 1)
     sub = {k: v[targets] for k, v in g.items()}
     compare(sub, ref, mean_rel=1e-3, var_rel=1e-2, int_rel=1e-2, label=f"{prec} full-size")
+
+
+def _bits(t: torch.Tensor) -> torch.Tensor:
+    return t.view(torch.int32) if t.dtype == torch.float32 else t
+
+
+@pytest.mark.parametrize("case", ["crop", "faulty_pi", "one_frame"])
+@pytest.mark.parametrize("prec", ENGINES)
+def test_run_hist_equals_per_frame_steps(lib, prec, case):
+    """The sequence call, which computes the cost bounds of frame n+1 in the
+    launch that resolves frame n, gives bit-identical outputs and states to
+    one step per frame (13x18 crop: ragged 4x4 blocks)."""
+    frames = 1 if case == "one_frame" else 4
+    wl = hist_workload(rows=13, cols=18, frames=frames)
+    P = wl.P
+    hists = [wl.hist[n].to(DEV).contiguous() for n in range(frames)]
+    pi_in = faulty = None
+    if case == "faulty_pi":
+        g0 = torch.Generator().manual_seed(5)
+        pi_in = torch.rand(frames * P, generator=g0).to(DEV)
+        faulty = (torch.rand(P, generator=g0) < 0.1).to(torch.uint8).to(DEV)
+    ctx = lib.Context(wl.params(), prec)
+    st = [lib.State.empty(P, DEV), lib.State.empty(P, DEV)]
+    ctx.state_init(st[0])
+    out = lib.Outputs.empty(frames * P, DEV)
+    ctx.run_hist(hists, st, out, pi_in=pi_in, faulty=faulty)
+    ref = [lib.State.empty(P, DEV), lib.State.empty(P, DEV)]
+    ctx.state_init(ref[0])
+    for n in range(frames):
+        o = lib.Outputs.empty(P, DEV)
+        ctx.step_hist(hists[n], ref[n % 2], ref[(n + 1) % 2], o,
+                      pi_in=None if pi_in is None else pi_in[n * P:(n + 1) * P], faulty=faulty)
+        for name in ("depth", "var", "intensity", "background", "pi0_next", "argmax"):
+            a = getattr(out, name)[n * P:(n + 1) * P]
+            assert torch.equal(_bits(a), _bits(getattr(o, name))), (prec, case, n, name)
+    fin, rfin = st[frames % 2], ref[frames % 2]
+    for a, b in zip((fin.m, fin.v, fin.pi, fin.b), (rfin.m, rfin.v, rfin.pi, rfin.b)):
+        assert torch.equal(_bits(a), _bits(b))
+    assert ctx.last_device_status() == 0
+
+
+def test_run_hist_full_size_equals_steps(lib):
+    """The benchmark's configuration (256x256, T=4096) for 3 frames: the
+    sequence call and per-frame steps agree bit for bit."""
+    wl = synth.config4(device=DEV, frames=3)
+    P = wl.P
+    ctx = lib.Context(wl.params(), "fp16x2")
+    st = [lib.State.empty(P, DEV), lib.State.empty(P, DEV)]
+    ctx.state_init(st[0])
+    out = lib.Outputs.empty(3 * P, DEV)
+    ctx.run_hist([wl.hist[n] for n in range(3)], st, out)
+    filt = lib.R3DFilter(wl.params(), "fp16x2", device=DEV)
+    for n in range(3):
+        o = filt.step(wl.hist[n])
+        assert torch.equal(_bits(out.depth[n * P:(n + 1) * P]), _bits(o.depth)), n
+        assert torch.equal(out.argmax[n * P:(n + 1) * P], o.argmax), n
+    assert torch.equal(_bits(st[1].m), _bits(filt.state.m))
+    assert ctx.last_device_status() == 0
