@@ -228,7 +228,7 @@ __device__ __forceinline__ void halo_components(const DevModel& M, const float* 
     const float V = (det ? halo[36 + idx] : M.v_flat) + M.sigma_rw2;
     C.m[k] = m;
     C.k2[k] = 0.5f * kLog2e / V;
-    C.w2[k] = M.lognu2[k] - 0.5f * (kLog2TwoPi + log2f(V));
+    C.w2[k] = M.lognu2[k] - 0.5f * (kLog2TwoPi + fast_log2(V));
   }
   merge_components(C);
 }
@@ -353,20 +353,18 @@ struct Moments {
 // Merge b into a with a symmetric rule: the larger maximum wins (the lower
 // depth on ties); the other's sums are rescaled and re-centred on it.
 __device__ __forceinline__ void merge_moments(Moments& a, const Moments& b) {
-  const bool other = (b.R > a.R) || (b.R == a.R && b.ref < a.ref);
-  const float wR = other ? b.R : a.R, wref = other ? b.ref : a.ref;
-  auto bring = [&](const Moments& x, float& s0, float& s1, float& s2) __attribute__((always_inline)) {
-    const float sc = (x.R == -INFINITY) ? 0.f : fast_exp2(x.R - wR);
-    s0 = x.S0 * sc;
-    s1 = x.S1 * sc;
-    s2 = x.S2 * sc;
-    const float delta = x.ref - wref;
-    s2 = fmaf(delta, fmaf(2.f, s1, delta * s0), s2);
-    s1 = fmaf(delta, s0, s1);
-  };
-  float a0, a1, a2, b0, b1, b2;
-  bring(a, a0, a1, a2);
-  bring(b, b0, b1, b2);
+  const float aR = a.R, aref = a.ref, bR = b.R, bref = b.ref;
+  const bool other = (bR > aR) || (bR == aR && bref < aref);
+  const float wR = other ? bR : aR, wref = other ? bref : aref;
+  const float sa = aR == -INFINITY ? 0.f : fast_exp2(aR - wR);
+  const float sb = bR == -INFINITY ? 0.f : fast_exp2(bR - wR);
+  float a0 = a.S0 * sa, a1 = a.S1 * sa, a2 = a.S2 * sa;
+  float b0 = b.S0 * sb, b1 = b.S1 * sb, b2 = b.S2 * sb;
+  const float da = aref - wref, db = bref - wref;
+  a2 = fmaf(da, fmaf(2.f, a1, da * a0), a2);
+  a1 = fmaf(da, a0, a1);
+  b2 = fmaf(db, fmaf(2.f, b1, db * b0), b2);
+  b1 = fmaf(db, b0, b1);
   a.S0 = a0 + b0;
   a.S1 = a1 + b1;
   a.S2 = a2 + b2;
@@ -403,7 +401,8 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
                                             const float* sh_h, const BlockLds& B, int lane) {
   constexpr bool kMfma = kEng != kEngValu;
   constexpr bool kSplit = kEng == kEngMfma16x2;
-  constexpr int U = 8 * NBP;  // taps per lane: W <= 32 NBP - 30 by construction of NBP
+  // taps per lane (j = g + 4 u): W <= 32 NBP - 30 by construction of NBP, so u < 8 NBP - 7
+  constexpr int U = 8 * NBP - 7;
   const int i16 = lane & 15, g = lane >> 4;
   const LanePix L = lane_pixel(M, G, io.hist, io.faulty, idx, i16, g);
   const int dhi = M.d_lo + M.D - 1;
@@ -424,10 +423,24 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
     B.halo[72 + lane] = hp;
   }
   float lmax = 0.f, K = 0.f;
+  // reference depth: the rounded mean of the pixel's own prior component,
+  // read directly so that the gather of its cost starts at once
+  float mown = M.m_flat;
   if (L.valid) {
     const TileBound bv = bound[L.p];
     lmax = bv.x;
     K = bv.y;
+    const float pm = io.pm[L.p];
+    mown = io.ppi[L.p] > 0.5f ? pm : M.m_flat;
+  }
+  const int dref = (int)fminf(fmaxf(rintf(mown), (float)M.d_lo), (float)dhi);
+  // exact cost at d_ref by an fp32 gather (the lane takes taps j = g + 4 u)
+  float zr[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = g + 4 * u;
+    const int t = dref - M.c + j;
+    zr[u] = (L.has_data && j < M.W && t >= 0 && t < M.T) ? half_bits_to_float(row[t]) : 0.f;
   }
   if constexpr (kMfma) lmax = lmax * (1.0f + 0x1p-9f) + K * (kSplit ? 2048.0f : 1.0f) * 0x1p-23f;
   const float cs2 = M.scale2 * (kSplit ? (1.0f / 2048.0f) : 1.0f);  // raw cost -> log2 units
@@ -435,25 +448,11 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
 
   Comps C;
   halo_components(M, B.halo, i16, C);
-  // reference depth: the rounded mean of the pixel's own prior component;
-  // its exact cost by an fp32 gather (the lane takes taps j = g + 4 u)
-  const int cidx = ((i16 >> 2) + 1) * 6 + (i16 & 3) + 1;
-  const float mown = (L.valid && B.halo[72 + cidx] > 0.5f) ? B.halo[cidx] : M.m_flat;
-  const int dref = (int)fminf(fmaxf(rintf(mown), (float)M.d_lo), (float)dhi);
   float lref = 0.f;
-  {
-    float zr[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = g + 4 * u;
-      const int t = dref - M.c + j;
-      zr[u] = (L.has_data && j < M.W && t >= 0 && t < M.T) ? half_bits_to_float(row[t]) : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = g + 4 * u;
-      if (j < M.W) lref = fmaf(sh_h[j], zr[u], lref);
-    }
+  for (int u = 0; u < U; ++u) {
+    const int j = g + 4 * u;
+    if (j < M.W) lref = fmaf(sh_h[j], zr[u], lref);
   }
   lref = group_sum<16, 32>(lref);
 
@@ -475,24 +474,23 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
   // candidate depth some component reaches theta, so components below
   // theta - kLiveGap change f by less than 9 * 2^-kLiveGap relative and are
   // skipped; depths where no component is live are not candidates at all.
-  // The block keeps, per component, the tile range covering every lane's
-  // live interval.
+  // The block keeps, per component, the tile range covering every pixel's
+  // live interval (LDS min / max over the pixels).
+  if (lane < 9) {
+    B.trange[lane] = 0x7fffffff;
+    B.trange[9 + lane] = -1;
+  }
+  wave_sync();
+  if (L.valid && g == 0) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const bool lv = L.valid && C.w2[k] >= theta - kLiveGap;
-    const float R = lv ? sqrtf((C.w2[k] - theta + kLiveGap) / C.k2[k]) + 2.0f : 0.f;
-    float lo = lv ? C.m[k] - R : INFINITY;
-    float hi = lv ? C.m[k] + R : -INFINITY;
-#pragma unroll
-    for (int xm = 1; xm <= 32; xm <<= 1) {
-      lo = fminf(lo, __shfl_xor(lo, xm));
-      hi = fmaxf(hi, __shfl_xor(hi, xm));
-    }
-    lo = fmaxf(lo, (float)M.d_lo);
-    hi = fminf(hi, (float)dhi);
-    if (lane == 0) {
-      B.trange[k] = lo <= hi ? ((int)floorf(lo) - M.d_lo) >> 4 : 1;
-      B.trange[9 + k] = lo <= hi ? ((int)ceilf(hi) - M.d_lo) >> 4 : 0;
+    for (int k = 0; k < 9; ++k) {
+      if (!(C.w2[k] >= theta - kLiveGap)) continue;
+      const float R = sqrtf((C.w2[k] - theta + kLiveGap) / C.k2[k]) + 2.0f;
+      const float lo = fmaxf(C.m[k] - R, (float)M.d_lo);
+      const float hi = fminf(C.m[k] + R, (float)dhi);
+      if (!(lo <= hi)) continue;
+      atomicMin(&B.trange[k], ((int)floorf(lo) - M.d_lo) >> 4);
+      atomicMax(&B.trange[9 + k], ((int)ceilf(hi) - M.d_lo) >> 4);
     }
   }
 
@@ -710,7 +708,7 @@ template <int kEng, int NBP>
 __device__ __forceinline__ void resolve_finish(const DevModel& M, const TileGeom& G,
                                                const StepIO& io, const TileBound* __restrict__ bound,
                                                int idx, const float* sh_irf, Moments mo, int lane) {
-  constexpr int U = 8 * NBP;
+  constexpr int U = 8 * NBP - 7;  // taps per lane, as in resolve_prep
   const int i16 = lane & 15, g = lane >> 4;
   const LanePix L = lane_pixel(M, G, io.hist, io.faulty, idx, i16, g);
   const uint16_t* row = io.hist + (size_t)L.p * M.T;
@@ -823,13 +821,12 @@ __device__ __forceinline__ void resolve_group(const DevModel& M, const TileGeom&
     sp[4 * 64 + lane] = part.S2;
     __syncthreads();
     if (wave == d) {
-      for (int w = 0; w < 4; ++w) {
+      mo = Moments{s_part[lane], s_part[64 + lane], s_part[128 + lane], s_part[192 + lane],
+                   s_part[256 + lane]};
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
         const float* q = s_part + w * 5 * 64;
-        const Moments o{q[lane], q[64 + lane], q[128 + lane], q[192 + lane], q[256 + lane]};
-        if (w == 0)
-          mo = o;
-        else
-          merge_moments(mo, o);
+        merge_moments(mo, Moments{q[lane], q[64 + lane], q[128 + lane], q[192 + lane], q[256 + lane]});
       }
     }
     __syncthreads();
@@ -872,7 +869,7 @@ __device__ __forceinline__ void tile_prologue(const DevModel& M, const TileGeom&
 // work left. Resolve workgroup j takes blocks w * nr + j (w = its
 // wavefronts); bound workgroup j's wavefront w takes blocks 4 j + w + 4 nb k.
 template <int kEng, int NBP>
-__global__ void __launch_bounds__(256) k_tile(DevModel M, TileGeom G, TileJob J) {
+__global__ void __launch_bounds__(256, NBP <= 3 ? 4 : 2) k_tile(DevModel M, TileGeom G, TileJob J) {
   extern __shared__ __align__(16) unsigned char smem[];
   tile_prologue<kEng, NBP>(M, G, smem);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
