@@ -6,14 +6,20 @@ timing bins, fp16 photon-count histograms (signal Poisson(50) spread by a
 sigma = 6 bin IRF with 64 taps, background Poisson(400) uniform), beta = 0.5,
 3x3 spatio-temporal fusion. One step = one pass of the whole per-frame path
 (a1..a7: cost, prior, argmax/moments, state update, background/reflectivity,
-prior presence) over the 30 frames, starting from the initial state. Inputs
-are drawn on the device before timing (15 GiB resident in HBM).
+prior presence) over the 30 frames, starting from the initial state, through
+the sequence entry point r3d_run_hist (31 launches of the tile kernel: the
+cost bounds of frame n+1 are computed in the launch that resolves frame n).
+Inputs are drawn on the device before timing (15 GiB resident in HBM).
 
 Prints one JSON line with the matrix-core form's pixel-frames/s, the plain
-fp32 form's rate on the same workload, the roofline of the step kernel
-(HBM-bound: algorithmic bytes per launch over the launch time measured with
-events on the launch stream) and the FP64 CPU oracle's rate on a bounded
-sample.
+fp32 form's rate on the same workload and entry point, the roofline of the
+tile kernel (HBM-bound: algorithmic bytes per launch over the average launch
+time, measured with events on the launch stream) and the FP64 CPU oracle's
+rate on a bounded sample.
+
+``--traffic-probe`` runs 4 frames of the sequence call, then a 512 MiB
+device copy, and exits: the driver of the rocprofv3 counter runs whose
+results are recorded under profiles/.
 """
 import argparse
 import json
@@ -34,7 +40,7 @@ def algorithmic_bytes_per_pixel_frame(T: int) -> int:
     return 2 * T + 16 + 16 + 24
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_tile_fp16x2_hist256x256x4096.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_tile_fp16x2_hist256x256x4096.json")
 KERNEL_SRCS = ["paper_2004_09211_amd/csrc/k_tile.hip", "paper_2004_09211_amd/csrc/r3d_device.hpp",
                "paper_2004_09211_amd/csrc/r3d_tile.hpp"]
 
@@ -49,7 +55,40 @@ def measured_traffic(precision: str, frames: int):
     sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in KERNEL_SRCS))
     if sha.hexdigest()[:16] != rec["kernel_src_sha"]:
         return None
-    return (rec["first_frame_bytes"] + (frames - 1) * rec["steady_frame_bytes"]) / frames
+    # launches of a sequence of F frames: the bounds of frame 0; the resolve
+    # of frame 0 (flat initial prior: every tile a candidate) with the bounds
+    # of frame 1; F - 2 steady launches; the resolve of the last frame
+    if frames < 2:
+        return None
+    total = (rec["bound_only_launch_bytes"] + rec["first_pipelined_launch_bytes"]
+             + (frames - 2) * rec["steady_launch_bytes"] + rec["resolve_only_launch_bytes"])
+    return round(total / (frames + 1))
+
+
+def traffic_probe():
+    """Counter driver: 4 frames of the sequence call on the benchmark's
+    workload, then a 512 MiB device-to-device copy (an elementwise kernel
+    reading and writing 512 MiB) that calibrates FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    import synth
+    from paper_2004_09211_amd import r3d
+    r3d.load()
+    dev = torch.device("cuda:0")
+    wl = synth.config4(seed=0, device=dev, frames=4)
+    ctx = r3d.Context(wl.params(), "fp16x2")
+    st = [r3d.State.empty(wl.P, dev), r3d.State.empty(wl.P, dev)]
+    out = r3d.Outputs.empty(4 * wl.P, dev)
+    ctx.state_init(st[0])
+    ctx.run_hist([wl.hist[n] for n in range(4)], st, out)
+    torch.cuda.synchronize()
+    src = torch.ones(512 * 2**20 // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    if ctx.last_device_status() != 0:
+        raise RuntimeError("device status")
+    print("traffic probe done", flush=True)
 
 
 def run_gpu(args):
@@ -74,33 +113,43 @@ def run_gpu(args):
         out = r3d.Outputs.empty(P, dev)
         return ctx, st, out
 
-    def sequence(ctx, st, out, ev=None):
-        ctx.state_init(st[0])
-        for n in range(F):
-            if ev is not None:
-                ev[0][n].record()
-            ctx.step_hist(wl.hist[n], st[n % 2], st[(n + 1) % 2], out)
-            if ev is not None:
-                ev[1][n].record()
+    hists = [wl.hist[n] for n in range(F)]
 
-    def timed(precision, steps, warmup):
-        ctx, st, out = make(precision)
+    def sequence(ctx, st, out, ev=None, per_frame=False):
+        ctx.state_init(st[0])
+        if ev is not None:
+            ev[0].record()
+        if per_frame:
+            # one r3d_step_hist per frame (bounds, then resolve: 2 launches)
+            for n in range(F):
+                ctx.step_hist(hists[n], st[n % 2], st[(n + 1) % 2], out)
+        else:
+            ctx.run_hist(hists, st, out)
+        if ev is not None:
+            ev[1].record()
+
+    def timed(precision, steps, warmup, per_frame=False):
+        ctx = r3d.Context(params, precision)
+        st = [r3d.State.empty(P, dev), r3d.State.empty(P, dev)]
+        out = r3d.Outputs.empty((1 if per_frame else F) * P, dev)
         for _ in range(warmup):
-            sequence(ctx, st, out)
+            sequence(ctx, st, out, per_frame=per_frame)
         torch.cuda.synchronize()
-        evs = [([torch.cuda.Event(enable_timing=True) for _ in range(F)],
-                [torch.cuda.Event(enable_timing=True) for _ in range(F)]) for _ in range(steps)]
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(steps):
-            sequence(ctx, st, out, evs[s])
+            sequence(ctx, st, out, evs[s], per_frame=per_frame)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         status = ctx.last_device_status()
         if status != 0:
             raise RuntimeError(f"device status {status}")
-        launch_ms = [evs[s][0][n].elapsed_time(evs[s][1][n]) for s in range(steps) for n in range(F)]
-        return wall, sum(launch_ms) / len(launch_ms)
+        # launches of the tile kernel per step: F + 1 (sequence call) or 2 F
+        launches = 2 * F if per_frame else F + 1
+        launch_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * launches)
+        return wall, launch_ms
 
     prec = r3d.PRECISIONS[args.precision]
     wall, launch_ms = timed(prec, args.steps, args.warmup)
@@ -108,16 +157,21 @@ def run_gpu(args):
     value = P * F * args.steps / wall
     plain = None
     if args.plain_steps > 0 and prec != r3d.R3D_FP32:
-        pw, pl = timed(r3d.R3D_FP32, args.plain_steps, 1)
+        # the plain form at its faster entry point on this workload: one
+        # step per frame (its bound pass is vector-ALU bound and gains
+        # nothing from sharing launches with the resolve pass)
+        pw, pl = timed(r3d.R3D_FP32, args.plain_steps, 1, per_frame=True)
         plain = dict(value=P * F * args.plain_steps / pw, ms_per_step=1e3 * pw / args.plain_steps,
-                     launch_ms=pl, precision="fp32")
-    bytes_launch = algorithmic_bytes_per_pixel_frame(T) * P
+                     launch_ms=pl, precision="fp32", entry="r3d_step_hist per frame")
+    # algorithmic bytes of the F frames spread over the F + 1 launches
+    bytes_launch = algorithmic_bytes_per_pixel_frame(T) * P * F / (F + 1)
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=measured_traffic(args.precision, F),
-                kernel="r3d step (one launch per frame)", launch_ms=round(launch_ms, 5),
-                bytes_per_launch=bytes_launch)
+                kernel=f"k_tile ({F + 1} launches per {F}-frame sequence call: the cost bounds of "
+                       "frame n+1 in the launch that resolves frame n)",
+                launch_ms=round(launch_ms, 5), bytes_per_launch=round(bytes_launch))
     sample_hist = None
     if not args.no_cpu_baseline:
         r = args.cpu_rows
@@ -275,6 +329,7 @@ def main():
     ap.add_argument("--tune-cache", default="")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--grad-reps", type=int, default=5)
+    ap.add_argument("--traffic-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is measured on a single MI355X "
@@ -282,6 +337,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
+    if args.traffic_probe:
+        traffic_probe()
+        return
     res, sample = run_gpu(args)
     batched = None if args.no_batched else run_batched(args)
     gradient = None if args.no_grad else run_grad(args)

@@ -409,3 +409,17 @@ def test_fd_gradient_of_loss_is_consistent():
     lp = oracle.filter_loss(theta + eps * u, mdl, frames, truth)
     lm = oracle.filter_loss(theta - eps * u, mdl, frames, truth)
     assert (lp - lm) / (2 * eps) == pytest.approx(g @ u, rel=1e-4, abs=1e-8)
+
+
+def test_gaussian_irf_is_bin_integrated_pulse():
+    """Sec. II-A: the discrete IRF is the pulse integrated over each bin; it
+    is renormalised over its taps (Sec. II-D's unit integral) and peaks at
+    tap c. Checked against quadrature of the normal density."""
+    sigma, W, c = 3.7, 31, 15
+    irf = oracle.gaussian_irf_sigma(sigma, W, c)
+    ref = np.array([integrate.quad(stats.norm(0.0, sigma).pdf, j - c - 0.5, j - c + 0.5,
+                                   epsabs=1e-15, epsrel=1e-13)[0] for j in range(W)])
+    ref /= ref.sum()
+    np.testing.assert_allclose(irf, ref, rtol=1e-10, atol=1e-15)
+    assert int(np.argmax(irf)) == c and abs(irf.sum() - 1.0) < 1e-14
+    np.testing.assert_allclose(irf[c - 6:c], irf[c + 6:c:-1], rtol=1e-12)
