@@ -7,8 +7,8 @@ sigma = 6 bin IRF with 64 taps, background Poisson(400) uniform), beta = 0.5,
 3x3 spatio-temporal fusion. One step = one pass of the whole per-frame path
 (a1..a7: cost, prior, argmax/moments, state update, background/reflectivity,
 prior presence) over the 30 frames, starting from the initial state, through
-the sequence entry point r3d_run_hist (31 launches of the tile kernel: the
-cost bounds of frame n+1 are computed in the launch that resolves frame n).
+the sequence entry point r3d_run_hist (one launch of the tile kernel per
+frame).
 Inputs are drawn on the device before timing (15 GiB resident in HBM).
 
 Prints one JSON line with the matrix-core form's pixel-frames/s, the plain
@@ -55,14 +55,13 @@ def measured_traffic(precision: str, frames: int):
     sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in KERNEL_SRCS))
     if sha.hexdigest()[:16] != rec["kernel_src_sha"]:
         return None
-    # launches of a sequence of F frames: the bounds of frame 0; the resolve
-    # of frame 0 (flat initial prior: every tile a candidate) with the bounds
-    # of frame 1; F - 2 steady launches; the resolve of the last frame
-    if frames < 2:
+    # one launch per frame: frame 0 (flat initial prior), frame 1 (the prior
+    # left by frame 0), then F - 2 steady launches
+    if frames < 3:
         return None
-    total = (rec["bound_only_launch_bytes"] + rec["first_pipelined_launch_bytes"]
-             + (frames - 2) * rec["steady_launch_bytes"] + rec["resolve_only_launch_bytes"])
-    return round(total / (frames + 1))
+    total = (rec["frame0_launch_bytes"] + rec["frame1_launch_bytes"]
+             + (frames - 2) * rec["steady_launch_bytes"])
+    return round(total / frames)
 
 
 def traffic_probe():
@@ -120,7 +119,7 @@ def run_gpu(args):
         if ev is not None:
             ev[0].record()
         if per_frame:
-            # one r3d_step_hist per frame (bounds, then resolve: 2 launches)
+            # one r3d_step_hist per frame
             for n in range(F):
                 ctx.step_hist(hists[n], st[n % 2], st[(n + 1) % 2], out)
         else:
@@ -146,8 +145,8 @@ def run_gpu(args):
         status = ctx.last_device_status()
         if status != 0:
             raise RuntimeError(f"device status {status}")
-        # launches of the tile kernel per step: F + 1 (sequence call) or 2 F
-        launches = 2 * F if per_frame else F + 1
+        # launches of the tile kernel per step: one per frame
+        launches = F
         launch_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * launches)
         return wall, launch_ms
 
@@ -157,20 +156,17 @@ def run_gpu(args):
     value = P * F * args.steps / wall
     plain = None
     if args.plain_steps > 0 and prec != r3d.R3D_FP32:
-        # the plain form at its faster entry point on this workload: one
-        # step per frame (its bound pass is vector-ALU bound and gains
-        # nothing from sharing launches with the resolve pass)
+        # the plain form (fp32 vector FMAs) through the per-frame entry point
         pw, pl = timed(r3d.R3D_FP32, args.plain_steps, 1, per_frame=True)
         plain = dict(value=P * F * args.plain_steps / pw, ms_per_step=1e3 * pw / args.plain_steps,
                      launch_ms=pl, precision="fp32", entry="r3d_step_hist per frame")
-    # algorithmic bytes of the F frames spread over the F + 1 launches
-    bytes_launch = algorithmic_bytes_per_pixel_frame(T) * P * F / (F + 1)
+    # algorithmic bytes of one frame per launch
+    bytes_launch = algorithmic_bytes_per_pixel_frame(T) * P
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=measured_traffic(args.precision, F),
-                kernel=f"k_tile ({F + 1} launches per {F}-frame sequence call: the cost bounds of "
-                       "frame n+1 in the launch that resolves frame n)",
+                kernel=f"k_tile_step (one launch per frame, {F}-frame sequence call)",
                 launch_ms=round(launch_ms, 5), bytes_per_launch=round(bytes_launch))
     sample_hist = None
     if not args.no_cpu_baseline:

@@ -150,10 +150,9 @@ r3d_status r3d_step_hist(r3d_ctx *ctx, const uint16_t *hist,
                          const r3d_out *out, void *stream);
 
 /* Consecutive frames of fp16 histograms through Algorithm 1 (Sec. III-B),
- * each frame exactly as r3d_step_hist computes it (bit-identical results),
- * with the work of neighbouring frames overlapped: the cost of a frame is
- * bounded (its maximum over the depth grid, which needs no filter state) in
- * the same launch that resolves the previous frame's pseudo-posterior.
+ * each frame exactly as r3d_step_hist computes it (bit-identical results):
+ * one launch of the tile kernel per frame on the given stream, with no host
+ * round trip between frames.
  * hist: HOST array of nframes DEVICE pointers, each fp16 [P][T] as for
  * r3d_step_hist and 16-byte aligned (else R3D_EUNSUPPORTED). Frame n reads
  * state[n % 2] and writes state[(n + 1) % 2]; state[0] holds the state before

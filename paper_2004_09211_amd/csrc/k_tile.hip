@@ -1,5 +1,5 @@
 // Per-frame step on fp16 histograms, one wavefront per 4x4 pixel block, in
-// two passes that can run a frame apart.
+// one pass over the histograms.
 //
 // Cost (a3). For a 16-bin depth tile [d0, d0+16) the cost of the 16 pixels is
 // a banded Toeplitz product C[d][p] = sum_t H[d][t] Z[t][p] with
@@ -15,29 +15,23 @@
 // (kEngMfma16x2); fp32 vector FMAs from an LDS copy of the blocks (kEngValu,
 // the plain form).
 //
-// Bound pass. Streams every block of the frame and keeps, per pixel, the
-// maximum of the cost over the grid (matrix engines: of the fp16-hi part,
-// which bounds the exact cost within a relative 2^-10 plus K 2^-24) and the
-// photon count K. It reads nothing of the filter state, so the bounds of
-// frame n+1 can be computed while frame n is resolved.
-//
-// Resolve pass (a4..a7). The prior mixture of each pixel comes from the
-// previous states of the block's 6x6 halo. With lmax the cost bound, the
-// exact cost at a reference depth d_ref (the rounded mean of the pixel's own
-// prior component, gathered directly in fp32) and L = ell + log f the log2
-// pseudo-posterior, its maximum L* satisfies
-//   L* >= max(lmax + min_grid log f, ell(d_ref) + log f(d_ref)),
-// and L(d) <= lmax + max_k q_k(d) + log2(9). Per prior component this leaves
-// the interval of depths where L can reach L* - 160 (log2 units): outside
-// every interval exp2(L - L*) is below the smallest fp32 denormal, so those
-// depths contribute exactly zero weight and cannot be the argmax. The 16-bin
-// tiles meeting any pixel's interval are candidates; the blocks their pairs
-// read are streamed once through a register ring, the exact cost is
-// recomputed on the candidate tiles, and the argmax and the centred moments
-// are accumulated online (running maximum with rescaled, re-centred sums;
-// the four lanes of a pixel merge with a symmetric rule, so all of them hold
-// bit-identical results). Then the state update (a6) and the reflectivity /
-// background MLE (a7).
+// Posterior (a4, a5). Before the stream, each pixel's prior mixture comes
+// from the previous states of the block's 6x6 halo, and the exact cost at a
+// reference depth d_ref (the rounded mean of the pixel's own prior component)
+// is gathered in fp32. With L = ell + log f the log2 pseudo-posterior,
+// Llb = ell(d_ref) + log f(d_ref) <= L*, and with a margin Lambda = ell(d_ref)
+// + kLambdaGap, every depth d where ell(d) <= Lambda and every prior component
+// is below X = log f(d_ref) - 160 - log2(9) - kLambdaGap satisfies
+// L(d) < Llb - 160 <= L* - 160: exp2(L - L*) is below the smallest fp32
+// denormal, so d contributes exactly zero weight and cannot be the argmax.
+// Per component, q_k >= X holds on an interval; the 16-bin tiles meeting any
+// pixel's interval are candidates. The stream computes the exact cost of
+// every pair of tiles; a pair is evaluated when it holds a candidate tile or
+// when some pixel's cost in it exceeds Lambda (then with every component of
+// the mixture). The argmax and the centred moments are accumulated online
+// (running maximum with rescaled, re-centred sums; the four lanes of a pixel
+// merge with a symmetric rule, so all of them hold bit-identical results).
+// Then the state update (a6) and the reflectivity / background MLE (a7).
 #include "r3d_device.hpp"
 #include "r3d_tile.hpp"
 
@@ -45,6 +39,8 @@ namespace r3d {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushort2 __attribute__((ext_vector_type(2)));
+typedef _Float16 half2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRingT = 256;            // LDS ring per pixel (fp16 bins), VALU engine
@@ -56,11 +52,12 @@ constexpr int kBufWord3 = 0x00020000;   // raw buffer descriptor, 32-bit data fo
 constexpr int kHaloBytes = 448;         // 6x6 halo of (m, v, pi), 108 floats
 constexpr int kCompBytes = 9 * 3 * 16 * 4;  // (m, k2, w2) of 9 components x 16 pixels
 
-// blocks in flight per wavefront (beyond the blocks of the current pair)
-template <int kEng> struct TilePF {
-  static constexpr int bound = kEng == kEngValu ? 3 : 10;
-  static constexpr int resolve = kEng == kEngValu ? 3 : 5;
-};
+// blocks in flight per wavefront, beyond the blocks of the current pair
+template <int kEng> constexpr int kTilePF = kEng == kEngValu ? 3 : 6;
+constexpr float kLambdaGap = 32.f;  // log2 units: cost margin above ell(d_ref)
+// absolute slack of the fp16-hi cost in the split engine's raw units (hi
+// scaled by 2^11): 256 taps x count 2048 x 2^-25 x 2^11
+constexpr float kHiSlack = 256.f * 2048.f * 0x1p-25f * 2048.f;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -233,116 +230,6 @@ __device__ __forceinline__ void halo_components(const DevModel& M, const float* 
   merge_components(C);
 }
 
-// ============================ bound pass ============================
-// Streams every pair of the block through the ring (the blocks of the
-// current pair plus PF prefetched ones), counts photons, validates counts,
-// and writes (lmax, K) per pixel. The cost is >= 0, so its fp32 maximum is
-// the integer maximum of the bit patterns.
-template <int kEng, int NBP>
-__device__ __forceinline__ void bound_block(const DevModel& M, const TileGeom& G,
-                                            const uint16_t* hist, const uint8_t* faulty,
-                                            TileBound* __restrict__ bound, int idx,
-                                            const half8 (&Ahi)[2][NBP], _Float16* ring_lds,
-                                            int lane) {
-  constexpr bool kMfma = kEng != kEngValu;
-  constexpr int RING = NBP + TilePF<kEng>::bound;
-  const int i16 = lane & 15, g = lane >> 4;
-  const LanePix L = lane_pixel(M, G, hist, faulty, idx, i16, g);
-
-  float Kv = 0.f;
-  floatx4 Kacc = {0.f, 0.f, 0.f, 0.f};  // photon count via a ones-row contraction
-  ushort8 vmax = {0, 0, 0, 0, 0, 0, 0, 0};
-  half8 ones;
-#pragma unroll
-  for (int s = 0; s < 8; ++s) ones[s] = (_Float16)1.f;
-  auto account = [&](half8 v) __attribute__((always_inline)) {
-    vmax = __builtin_elementwise_max(vmax, __builtin_bit_cast(ushort8, v));
-    if constexpr (kMfma) {
-      Kacc = mfma16(ones, v, Kacc);
-    } else {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) Kv += (float)v[s];
-    }
-  };
-  auto fetch = [&](int kb) __attribute__((always_inline)) -> half8 {
-    return load_block(M, L, g, kb <= G.kb_last ? kb : -1);
-  };
-
-  unsigned lmax_bits = 0u;
-  half8 ring[RING];
-#pragma unroll
-  for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + x);
-  for (int m0 = 0; m0 < G.npairs; m0 += RING) {
-#pragma unroll
-    for (int u = 0; u < RING; ++u) {
-      const int m = m0 + u;
-      ring[(u + RING - 1) % RING] = fetch(G.kbA0 + m + RING - 1);
-      if (m < G.npairs) {
-      if constexpr (!kMfma) {
-        wave_sync();
-        if (m == 0) {
-#pragma unroll
-          for (int b = 0; b < NBP; ++b) ring_store(ring_lds, i16, g, G.kbA0 + b, ring[(u + b) % RING]);
-        } else {
-          ring_store(ring_lds, i16, g, G.kbA0 + m + NBP - 1, ring[(u + NBP - 1) % RING]);
-        }
-        wave_sync();
-      }
-      if (m == 0) {
-#pragma unroll
-        for (int b = 0; b < NBP - 1; ++b) account(ring[(u + b) % RING]);
-      }
-      account(ring[(u + NBP - 1) % RING]);
-      floatx4 c0, c1;
-      if constexpr (kMfma) {
-        c0 = floatx4{0.f, 0.f, 0.f, 0.f};
-        c1 = c0;
-#pragma unroll
-        for (int b = 0; b < NBP; ++b) {
-          c0 = mfma16(Ahi[0][b], ring[(u + b) % RING], c0);
-          c1 = mfma16(Ahi[1][b], ring[(u + b) % RING], c1);
-        }
-      } else {
-        c0 = valu_tile(M, ring_lds, i16, g, m, 0);
-        c1 = valu_tile(M, ring_lds, i16, g, m, 1);
-      }
-      const unsigned a = __builtin_elementwise_max(__float_as_uint(c0[0]), __float_as_uint(c0[1]));
-      const unsigned b = __builtin_elementwise_max(__float_as_uint(c0[2]), __float_as_uint(c0[3]));
-      const unsigned c = __builtin_elementwise_max(__float_as_uint(c1[0]), __float_as_uint(c1[1]));
-      const unsigned d = __builtin_elementwise_max(__float_as_uint(c1[2]), __float_as_uint(c1[3]));
-      lmax_bits = __builtin_elementwise_max(lmax_bits, __builtin_elementwise_max(
-                      __builtin_elementwise_max(a, b), __builtin_elementwise_max(c, d)));
-      }
-    }
-  }
-  // blocks of [0, T) that no depth window reaches still hold photons
-  for (int kb = 0; kb < G.nkb; ++kb) {
-    if (kb >= G.kbA0 && kb <= G.kb_last) continue;
-    account(load_block(M, L, g, kb));
-  }
-  unsigned bad = 0;
-#pragma unroll
-  for (int s = 0; s < 8; ++s) bad |= vmax[s] > 0x6800u ? kErrOverflow : 0u;  // > 2048 or negative
-  if (bad) atomicOr(M.err, bad);
-
-  const float K = kMfma ? Kacc[0] : group_sum<16, 32>(Kv);
-  lmax_bits = max(lmax_bits, (unsigned)__shfl_xor((int)lmax_bits, 16));
-  lmax_bits = max(lmax_bits, (unsigned)__shfl_xor((int)lmax_bits, 32));
-  if (L.valid && g == 0) bound[L.p] = make_float2(__uint_as_float(lmax_bits), K);
-}
-
-// ============================ resolve pass ============================
-// A resolve workgroup takes the four blocks w * nr + j (w = its wavefronts),
-// so the border blocks, first in block order, land one per workgroup. Each
-// wavefront prepares its own block (prior, bounds, candidate masks, all in
-// its LDS region); the candidate pairs of a block are then evaluated by its
-// own wavefront, except for blocks with many needed histogram blocks (the
-// border blocks, whose flat prior components make every depth a candidate),
-// whose stream is split into four consecutive ranges, one per wavefront of
-// the workgroup. Partial moments are merged in wavefront order, so the
-// result depends only on the inputs.
-constexpr int kSplitMin = 24;  // needed blocks above which a block is shared
-
 // Online argmax and centred moments of the log2 pseudo-posterior: running
 // maximum R at depth ref and sums S0 = sum w, S1 = sum w (d - ref),
 // S2 = sum w (d - ref)^2 with w = exp2(L - R).
@@ -372,6 +259,21 @@ __device__ __forceinline__ void merge_moments(Moments& a, const Moments& b) {
   a.ref = wref;
 }
 
+// Merge the four lanes of each pixel (lanes i16, i16 + 16, i16 + 32,
+// i16 + 48); all four end with the same moments.
+__device__ __forceinline__ void lane_merge(Moments& mo) {
+#pragma unroll
+  for (int xm = 16; xm <= 32; xm <<= 1) {
+    Moments o;
+    o.R = __shfl_xor(mo.R, xm);
+    o.ref = __shfl_xor(mo.ref, xm);
+    o.S0 = __shfl_xor(mo.S0, xm);
+    o.S1 = __shfl_xor(mo.S1, xm);
+    o.S2 = __shfl_xor(mo.S2, xm);
+    merge_moments(mo, o);
+  }
+}
+
 // Per-wavefront LDS region of a resolved block.
 struct BlockLds {
   unsigned *tmask, *pmask, *nmask;
@@ -393,18 +295,18 @@ __device__ __forceinline__ BlockLds block_lds(const TileGeom& G, unsigned char* 
   return B;
 }
 
-// Prior, bounds and candidate masks of block idx into its LDS region;
-// returns the number of needed histogram blocks (wave-uniform).
+// Prior, reference cost and candidate tiles of block idx into its LDS
+// region; returns the lane's cost margin Lambda (log2 units) and the
+// components live for some pixel (wave-uniform).
 template <int kEng, int NBP>
-__device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G, const StepIO& io,
-                                            const TileBound* __restrict__ bound, int idx,
-                                            const float* sh_h, const BlockLds& B, int lane) {
+__device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, const StepIO& io,
+                                          const LanePix& L, const float* sh_h, const BlockLds& B,
+                                          int lane, float& Lam, unsigned& wave_live) {
   constexpr bool kMfma = kEng != kEngValu;
   constexpr bool kSplit = kEng == kEngMfma16x2;
   // taps per lane (j = g + 4 u): W <= 32 NBP - 30 by construction of NBP, so u < 8 NBP - 7
   constexpr int U = 8 * NBP - 7;
   const int i16 = lane & 15, g = lane >> 4;
-  const LanePix L = lane_pixel(M, G, io.hist, io.faulty, idx, i16, g);
   const int dhi = M.d_lo + M.D - 1;
   const uint16_t* row = io.hist + (size_t)L.p * M.T;
 
@@ -422,14 +324,10 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
     B.halo[36 + lane] = hv;
     B.halo[72 + lane] = hp;
   }
-  float lmax = 0.f, K = 0.f;
   // reference depth: the rounded mean of the pixel's own prior component,
   // read directly so that the gather of its cost starts at once
   float mown = M.m_flat;
   if (L.valid) {
-    const TileBound bv = bound[L.p];
-    lmax = bv.x;
-    K = bv.y;
     const float pm = io.pm[L.p];
     mown = io.ppi[L.p] > 0.5f ? pm : M.m_flat;
   }
@@ -442,8 +340,6 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
     const int t = dref - M.c + j;
     zr[u] = (L.has_data && j < M.W && t >= 0 && t < M.T) ? half_bits_to_float(row[t]) : 0.f;
   }
-  if constexpr (kMfma) lmax = lmax * (1.0f + 0x1p-9f) + K * (kSplit ? 2048.0f : 1.0f) * 0x1p-23f;
-  const float cs2 = M.scale2 * (kSplit ? (1.0f / 2048.0f) : 1.0f);  // raw cost -> log2 units
   wave_sync();
 
   Comps C;
@@ -456,24 +352,20 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
   }
   lref = group_sum<16, 32>(lref);
 
-  const float l2max = lmax * cs2;
-  float lbf = -INFINITY;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const float e = fmaxf(fabsf((float)M.d_lo - C.m[k]), fabsf((float)dhi - C.m[k]));
-    lbf = fmaxf(lbf, C.w2[k] - e * e * C.k2[k]);
-  }
-  unsigned wave_live = 0u;
+  wave_live = 0u;
 #pragma unroll
   for (int k = 0; k < 9; ++k) wave_live |= (__any(L.valid && (C.live >> k & 1u)) ? 1u : 0u) << k;
-  float Llb = l2max + lbf;
-  if (L.valid) Llb = fmaxf(Llb, fmaf(lref, M.scale2, log_prior2(C, (float)dref, wave_live)));
-  const float theta = Llb - kCullMargin2 - l2max - kLog2Nine;
+  const float lref2 = lref * M.scale2;
+  Lam = lref2 + kLambdaGap;
+  // X = Llb - 160 - Lambda - log2(9), with Llb = lref2 + log f(d_ref)
+  const float theta = L.valid
+      ? log_prior2(C, (float)dref, wave_live) - kCullMargin2 - kLambdaGap - kLog2Nine
+      : INFINITY;
 
   // Component k is "live" on depths where q_k >= theta - kLiveGap: at a
-  // candidate depth some component reaches theta, so components below
-  // theta - kLiveGap change f by less than 9 * 2^-kLiveGap relative and are
-  // skipped; depths where no component is live are not candidates at all.
+  // candidate depth of a pair whose costs stay below Lambda some component
+  // reaches theta, so components below theta - kLiveGap change f by less
+  // than 9 * 2^-kLiveGap relative and are skipped there.
   // The block keeps, per component, the tile range covering every pixel's
   // live interval (LDS min / max over the pixels).
   if (lane < 9) {
@@ -485,7 +377,7 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       if (!(C.w2[k] >= theta - kLiveGap)) continue;
-      const float R = sqrtf((C.w2[k] - theta + kLiveGap) / C.k2[k]) + 2.0f;
+      const float R = __builtin_amdgcn_sqrtf((C.w2[k] - theta + kLiveGap) * fast_rcp(C.k2[k])) + 2.0f;
       const float lo = fmaxf(C.m[k] - R, (float)M.d_lo);
       const float hi = fminf(C.m[k] + R, (float)dhi);
       if (!(lo <= hi)) continue;
@@ -510,7 +402,7 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       if ((k & 3) != g || !(C.w2[k] >= theta)) continue;
-      const float R = sqrtf((C.w2[k] - theta) / C.k2[k]) + 2.0f;
+      const float R = __builtin_amdgcn_sqrtf((C.w2[k] - theta) * fast_rcp(C.k2[k])) + 2.0f;
       const float lo = fmaxf(floorf(C.m[k] - R), (float)M.d_lo);
       const float hi = fminf(ceilf(C.m[k] + R), (float)dhi);
       if (!(lo <= hi)) continue;
@@ -529,205 +421,20 @@ __device__ __forceinline__ int resolve_prep(const DevModel& M, const TileGeom& G
     }
   }
   wave_sync();
-  // blocks read by the candidate pairs: block kbA0 + r is needed when a
-  // candidate pair starts at one of r - NBP + 1 .. r
-  for (int w = lane; w < G.need_words; w += 64) {
-    const unsigned cur = w < G.pair_words ? B.pmask[w] : 0u;
-    const unsigned prev = (w > 0 && w - 1 < G.pair_words) ? B.pmask[w - 1] : 0u;
-    unsigned acc = cur;
-#pragma unroll
-    for (int k = 1; k < NBP; ++k) acc |= (cur << k) | (prev >> (32 - k));
-    B.nmask[w] = acc;
-  }
-  wave_sync();
-  int nneed = 0;
-  for (int w = 0; w < G.need_words; ++w)
-    nneed += __builtin_popcount(__builtin_amdgcn_readfirstlane(B.nmask[w]));
-  return nneed;
 }
 
-// Evaluate the candidate pairs of block idx whose first block is at
-// positions [pos_lo, pos_hi) of its needed-block stream, accumulating into
-// mo. The block's masks, tile ranges and components come from its LDS region
-// B (prepared by its own wavefront); any wavefront may run this.
+// State update (a6) and reflectivity / background (a7) of block idx from
+// its moments (already merged over the four lanes of each pixel).
 template <int kEng, int NBP>
-__device__ __forceinline__ void resolve_range(const DevModel& M, const TileGeom& G,
-                                              const StepIO& io, int idx, const half8* sA,
-                                              const BlockLds& B, _Float16* ring_lds, int pos_lo,
-                                              int pos_hi, Moments& mo, int lane) {
-  constexpr bool kMfma = kEng != kEngValu;
-  constexpr bool kSplit = kEng == kEngMfma16x2;
-  constexpr int RING = NBP + TilePF<kEng>::resolve;
-  const int i16 = lane & 15, g = lane >> 4;
-  const LanePix L = lane_pixel(M, G, io.hist, io.faulty, idx, i16, g);
-  const int dhi = M.d_lo + M.D - 1;
-  const float cs2 = M.scale2 * (kSplit ? (1.0f / 2048.0f) : 1.0f);
-  // lane k < 9 holds component k's tile range (empty elsewhere), so the set
-  // of components live in a tile is one ballot
-  const int TAv = lane < 9 ? B.trange[lane] : 1, TBv = lane < 9 ? B.trange[9 + lane] : 0;
-  const float* comp = B.comp;
-
-  auto is_cand = [&](const unsigned* mk, int i) __attribute__((always_inline)) -> bool {
-    return (__builtin_amdgcn_readfirstlane(mk[i >> 5]) >> (i & 31)) & 1u;
-  };
-  // log2 pseudo-posterior of the lane's 4 depths of tile dt, online moments
-  auto tile_epi = [&](const floatx4& acc, int dt) __attribute__((always_inline)) {
-    const int dbase = M.d_lo + 16 * dt + 4 * g;
-    const unsigned tmk = (unsigned)__ballot(TAv <= dt && dt <= TBv) & 0x1ffu;
-    // log2 f by an online log-sum-exp over the live components
-    float mx[4], sm[4];
-    unsigned bits = tmk;
-    const bool single = __builtin_popcount(tmk) == 1;
-    {
-      const int k = bits ? __builtin_ctz(bits) : 0;
-      bits &= bits - 1u;
-      const float mk = comp[(3 * k) * 16 + i16], kk = comp[(3 * k + 1) * 16 + i16];
-      const float wk = tmk ? comp[(3 * k + 2) * 16 + i16] : -INFINITY;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float e = (float)(dbase + q) - mk;
-        mx[q] = fmaf(-e * e, kk, wk);
-        sm[q] = 1.f;
-      }
-    }
-    while (bits) {
-      const int k = __builtin_ctz(bits);
-      bits &= bits - 1u;
-      const float mk = comp[(3 * k) * 16 + i16], kk = comp[(3 * k + 1) * 16 + i16];
-      const float wk = comp[(3 * k + 2) * 16 + i16];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float e = (float)(dbase + q) - mk;
-        const float qv = fmaf(-e * e, kk, wk);
-        const float nm = fmaxf(mx[q], qv);
-        const float sa = nm == -INFINITY ? 0.f : fast_exp2(mx[q] - nm);
-        const float sb = nm == -INFINITY ? 0.f : fast_exp2(qv - nm);
-        sm[q] = fmaf(sm[q], sa, sb);
-        mx[q] = nm;
-      }
-    }
-    float Lq[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float lp = (single || mx[q] == -INFINITY) ? mx[q] : mx[q] + fast_log2(sm[q]);
-      Lq[q] = (L.valid && dbase + q <= dhi) ? fmaf(acc[q], cs2, lp) : -INFINITY;
-    }
-    float mt = Lq[0];
-    int qt = 0;
-#pragma unroll
-    for (int q = 1; q < 4; ++q)
-      if (Lq[q] > mt) {
-        mt = Lq[q];
-        qt = q;
-      }
-    if (mt > mo.R) {
-      const float sc = fast_exp2(mo.R - mt);
-      const float dnew = (float)(dbase + qt);
-      const float delta = mo.ref - dnew;
-      mo.S0 *= sc;
-      mo.S1 *= sc;
-      mo.S2 *= sc;
-      mo.S2 = fmaf(delta, fmaf(2.f, mo.S1, delta * mo.S0), mo.S2);
-      mo.S1 = fmaf(delta, mo.S0, mo.S1);
-      mo.R = mt;
-      mo.ref = dnew;
-    }
-    if (mt > -INFINITY) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float wq = fast_exp2(Lq[q] - mo.R);
-        const float e = (float)(dbase + q) - mo.ref;
-        mo.S0 += wq;
-        mo.S1 = fmaf(e, wq, mo.S1);
-        mo.S2 = fmaf(e * e, wq, mo.S2);
-      }
-    }
-  };
-
-  // Cursors over the set bits of the needed mask (wave-uniform), both
-  // starting at position pos_lo.
-  int lw = 0, skipped = 0;
-  unsigned lbits = G.need_words > 0 ? __builtin_amdgcn_readfirstlane(B.nmask[0]) : 0u;
-  while (lw < G.need_words) {
-    const int c = __builtin_popcount(lbits);
-    if (skipped + c > pos_lo) break;
-    skipped += c;
-    if (++lw < G.need_words) lbits = __builtin_amdgcn_readfirstlane(B.nmask[lw]);
-  }
-  for (; skipped < pos_lo && lw < G.need_words; ++skipped) lbits &= lbits - 1u;
-  int ew = lw;
-  unsigned ebits = lbits;
-  auto next_needed = [&](int& w, unsigned& bits) __attribute__((always_inline)) -> int {
-    while (bits == 0u) {
-      if (++w >= G.need_words) return -1;
-      bits = __builtin_amdgcn_readfirstlane(B.nmask[w]);
-    }
-    const int i = __builtin_ctz(bits);
-    bits &= bits - 1u;
-    return 32 * w + i;
-  };
-  // Stream the needed blocks in order through the ring; a candidate pair is
-  // evaluated at the position of its first block, whose NBP - 1 successors
-  // in the stream are its other blocks (all needed, hence consecutive).
-  // Every position issues exactly one load (past the last needed block, a
-  // load of nothing that returns zeros without touching memory), so the
-  // number of loads in flight after each block is known statically.
-  auto fetch = [&](int r) __attribute__((always_inline)) -> half8 {
-    return r >= 0 ? load_block(M, L, g, G.kbA0 + r) : load_nothing(L);
-  };
-  half8 ring[RING];
-#pragma unroll
-  for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(next_needed(lw, lbits));
-  for (int i0 = pos_lo; i0 < pos_hi; i0 += RING) {
-#pragma unroll
-    for (int u = 0; u < RING; ++u) {
-      ring[(u + RING - 1) % RING] = fetch(next_needed(lw, lbits));
-      const int m = i0 + u < pos_hi ? next_needed(ew, ebits) : -1;
-      if (m >= 0 && m < G.npairs && is_cand(B.pmask, m)) {
-        half8 blk[NBP];
-#pragma unroll
-        for (int b = 0; b < NBP; ++b) blk[b] = ring[(u + b) % RING];
-        if constexpr (!kMfma) {
-          wave_sync();
-#pragma unroll
-          for (int b = 0; b < NBP; ++b) ring_store(ring_lds, i16, g, G.kbA0 + m + b, blk[b]);
-          wave_sync();
-        }
-        floatx4 a0, a1;
-        pair_cost<kEng, NBP>(M, sA, ring_lds, lane, m, blk, a0, a1);
-        if (is_cand(B.tmask, 2 * m)) tile_epi(a0, 2 * m);
-        if (is_cand(B.tmask, 2 * m + 1)) tile_epi(a1, 2 * m + 1);
-      }
-    }
-  }
-}
-
-// Lane merge, state update (a6) and reflectivity / background (a7) of
-// block idx from its merged moments.
-template <int kEng, int NBP>
-__device__ __forceinline__ void resolve_finish(const DevModel& M, const TileGeom& G,
-                                               const StepIO& io, const TileBound* __restrict__ bound,
-                                               int idx, const float* sh_irf, Moments mo, int lane) {
-  constexpr int U = 8 * NBP - 7;  // taps per lane, as in resolve_prep
-  const int i16 = lane & 15, g = lane >> 4;
-  const LanePix L = lane_pixel(M, G, io.hist, io.faulty, idx, i16, g);
+__device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io, const LanePix& L,
+                                            const float* sh_irf, Moments mo, float K, int lane) {
+  constexpr int U = 8 * NBP - 7;  // taps per lane, as in step_prep
+  const int g = lane >> 4;
   const uint16_t* row = io.hist + (size_t)L.p * M.T;
-  // the four lanes of each pixel
-#pragma unroll
-  for (int xm = 16; xm <= 32; xm <<= 1) {
-    Moments o;
-    o.R = __shfl_xor(mo.R, xm);
-    o.ref = __shfl_xor(mo.ref, xm);
-    o.S0 = __shfl_xor(mo.S0, xm);
-    o.S1 = __shfl_xor(mo.S1, xm);
-    o.S2 = __shfl_xor(mo.S2, xm);
-    merge_moments(mo, o);
-  }
   const float mu = mo.S1 / mo.S0;
   const int dstar = (int)mo.ref;
   const float mean = mo.ref + mu;
   const float var = fmaxf(mo.S2 / mo.S0 - mu * mu, 0.f);
-  const float K = L.valid ? bound[L.p].y : 0.f;
 
   // ============================ a6 + a7 ============================
   const float pi_now = L.faulty ? 0.5f : (io.pi_in && L.valid ? io.pi_in[L.p] : 1.0f);
@@ -780,58 +487,366 @@ __device__ __forceinline__ void resolve_finish(const DevModel& M, const TileGeom
   }
 }
 
-// The resolve role of a workgroup: blocks w * nr + j for its wavefronts w.
+// ============================ shared blocks ============================
+// A block whose pairs are shared by the four wavefronts of its workgroup:
+// wavefront 0 prepares it and publishes its margins; its pairs are then
+// taken in chunks from a counter by wavefront 0 and, once their own blocks
+// are done, by the other three. Each chunk's moments go to a slot of their
+// own and are merged in chunk order, so the result does not depend on which
+// wavefront took which chunk.
+struct ShareLds {
+  unsigned* ctl;  // [0] published, [1] block shared, [2] next chunk, [3] live components
+  float* lam;     // [16] cost margin of each pixel
+  unsigned* K;    // [16] photon count of each pixel (integer sums: exact in any order)
+  float* slot;    // [kMaxChunks][5][16] moments of each chunk
+};
+
+constexpr int kShareBytes = (36 + kMaxChunks * 5 * 16) * 4;
+
+__device__ __forceinline__ ShareLds share_lds(const TileGeom& G, unsigned char* smem) {
+  ShareLds S;
+  S.ctl = reinterpret_cast<unsigned*>(smem + G.off_share);
+  S.lam = reinterpret_cast<float*>(S.ctl + 4);
+  S.K = S.ctl + 20;
+  S.slot = reinterpret_cast<float*>(S.ctl + 36);
+  return S;
+}
+
+__device__ __forceinline__ void put_moments(float* s, const Moments& mo, int i16) {
+  s[i16] = mo.R;
+  s[16 + i16] = mo.ref;
+  s[32 + i16] = mo.S0;
+  s[48 + i16] = mo.S1;
+  s[64 + i16] = mo.S2;
+}
+
+__device__ __forceinline__ Moments get_moments(const float* s, int i16) {
+  return Moments{s[i16], s[16 + i16], s[32 + i16], s[48 + i16], s[64 + i16]};
+}
+
+// ============================ one wavefront ============================
+// The wavefront's tasks: its own block (whole, or the first chunk when it is
+// wavefront 0 and its block is shared), then chunks of the shared block.
+// Each task streams its pairs through the register ring (the blocks of the
+// current pair plus kTilePF prefetched ones): photon count and count
+// validation on every block, the exact cost of both tiles of every pair, the
+// posterior on the pairs that need it. After the workgroup barrier each
+// wavefront finishes its own block (a6, a7).
 template <int kEng, int NBP>
-__device__ __forceinline__ void resolve_group(const DevModel& M, const TileGeom& G,
-                                              const TileJob& J, int j, const half8* sA,
-                                              const float* sh_irf, const float* sh_h,
-                                              unsigned char* smem, int wave, int lane) {
-  int* s_need = reinterpret_cast<int*>(smem + G.lds_share);
-  float* s_part = reinterpret_cast<float*>(smem + G.lds_share + 16);  // [4 waves][5][64 lanes]
-  const int idx = wave * J.nr + j;
-  const bool mine = idx < G.nblk;
-  const BlockLds B = block_lds(G, smem + G.lds_fixed + wave * G.lds_per_wave);
-  int nneed = 0;
-  if (mine) nneed = resolve_prep<kEng, NBP>(M, G, J.io, J.rbound, idx, sh_h, B, lane);
-  if (lane == 0) s_need[wave] = nneed;
-  __syncthreads();
-  // work items: 0 = the wavefront's own block when it is not shared, then
-  // the shared blocks in wavefront order (quarter w of the stream on
-  // wavefront w); one call site keeps the code compact
-  Moments mo{-INFINITY, 0.f, 0.f, 0.f, 0.f};
-  for (int it = 0; it < 5; ++it) {
-    const int d = it == 0 ? wave : it - 1;
-    const int nd = it == 0 ? nneed : s_need[d];
-    const int didx = d * J.nr + j;
-    if (didx >= G.nblk) continue;
-    if (it == 0 ? nd > kSplitMin : nd <= kSplitMin) continue;  // uniform over the workgroup for it > 0
-    const BlockLds D = block_lds(G, smem + G.lds_fixed + d * G.lds_per_wave);
-    Moments part{-INFINITY, 0.f, 0.f, 0.f, 0.f};
-    const int lo = it == 0 ? 0 : (wave * nd) / 4, hi = it == 0 ? nd : ((wave + 1) * nd) / 4;
-    resolve_range<kEng, NBP>(M, G, J.io, didx, sA, D, B.ring, lo, hi, part, lane);
-    if (it == 0) {
-      mo = part;
-      continue;
-    }
-    float* sp = s_part + wave * 5 * 64;
-    sp[0 * 64 + lane] = part.R;
-    sp[1 * 64 + lane] = part.ref;
-    sp[2 * 64 + lane] = part.S0;
-    sp[3 * 64 + lane] = part.S1;
-    sp[4 * 64 + lane] = part.S2;
-    __syncthreads();
-    if (wave == d) {
-      mo = Moments{s_part[lane], s_part[64 + lane], s_part[128 + lane], s_part[192 + lane],
-                   s_part[256 + lane]};
+__device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, const StepIO& io,
+                                          int idx, int wave, const half8* sA, const float* sh_irf,
+                                          const float* sh_h, unsigned char* smem, int lane) {
+  constexpr bool kMfma = kEng != kEngValu;
+  constexpr bool kSplit = kEng == kEngMfma16x2;
+  constexpr int RING = NBP + kTilePF<kEng>;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int dhi = M.d_lo + M.D - 1;
+  const float cs2 = M.scale2 * (kSplit ? (1.0f / 2048.0f) : 1.0f);  // raw cost -> log2 units
+  const bool active = idx < G.nblk;
+  unsigned char* wown = smem + G.lds_fixed + wave * G.lds_per_wave;
+  _Float16* ring_lds = block_lds(G, wown).ring;
+  const ShareLds S = share_lds(G, smem);
+
+  // current task: pairs [mb, me) of the block of L and B; c = its chunk, or
+  // -1 for a whole block
+  LanePix L = lane_pixel(M, G, io.hist, io.faulty, active ? idx : 0, i16, g);
+  BlockLds B = block_lds(G, wown);
+  int mb = 0, me = G.npairs, c = -1, kb_end = G.kb_last;
+  auto fetch = [&](int kb) __attribute__((always_inline)) -> half8 {
+    return load_block(M, L, g, kb <= kb_end ? kb : -1);
+  };
+  // the first blocks are in flight while the prior is prepared
+  half8 ring[RING];
+  if (active) {
 #pragma unroll
-      for (int w = 1; w < 4; ++w) {
-        const float* q = s_part + w * 5 * 64;
-        merge_moments(mo, Moments{q[lane], q[64 + lane], q[128 + lane], q[192 + lane], q[256 + lane]});
-      }
-    }
-    __syncthreads();
+    for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + x);
   }
-  if (mine) resolve_finish<kEng, NBP>(M, G, J.io, J.rbound, idx, sh_irf, mo, lane);
+  half8 Ahi[2][NBP];
+  if constexpr (kMfma) {
+#pragma unroll
+    for (int tau = 0; tau < 2; ++tau)
+#pragma unroll
+      for (int b = 0; b < NBP; ++b) Ahi[tau][b] = a_op(sA, NBP, 0, tau, b, lane);
+  }
+  float Lam = 0.f;
+  unsigned wave_live = 0u;
+  if (active) step_prep<kEng, NBP>(M, G, io, L, sh_h, B, lane, Lam, wave_live);
+  bool shared = false;
+  if (wave == 0) {
+    // a block with candidate tiles on most pairs (a frame border, a flat
+    // prior) is shared
+    int ncand = 0;
+    for (int w = 0; w < G.pair_words; ++w)
+      ncand += __builtin_popcount(__builtin_amdgcn_readfirstlane(B.pmask[w]));
+    shared = G.nchunks >= 2 && 4 * ncand >= G.npairs;
+    if (g == 0) {
+      S.lam[i16] = Lam;
+      S.K[i16] = 0u;
+    }
+    if (lane == 0) {
+      S.ctl[1] = shared ? 1u : 0u;
+      S.ctl[2] = 1u;
+      S.ctl[3] = wave_live;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) __hip_atomic_store(&S.ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (shared) {
+      c = 0;
+      me = G.chunk < G.npairs ? G.chunk : G.npairs;
+      kb_end = G.kbA0 + me + NBP - 2;
+    }
+  }
+
+  half8 ones;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) ones[s] = (_Float16)1.f;
+  auto is_cand = [&](const unsigned* mk, int i) __attribute__((always_inline)) -> bool {
+    return (__builtin_amdgcn_readfirstlane(mk[i >> 5]) >> (i & 31)) & 1u;
+  };
+
+  // first: the task is the wavefront's own block, whose first ring blocks
+  // are already loaded (a wavefront without a block starts with a chunk)
+  bool have = active, first = active, helping = false;
+  for (;;) {
+    if (have) {
+      if (!first) {
+#pragma unroll
+        for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + mb + x);
+      }
+      const int* trange = B.trange;
+      const float* comp = B.comp;
+      Moments mo{-INFINITY, 0.f, 0.f, 0.f, 0.f};
+      auto tile_epi = [&](const floatx4& acc, int dt, bool all) __attribute__((always_inline)) {
+        const int dbase = M.d_lo + 16 * dt + 4 * g;
+        unsigned tmk = wave_live;
+        if (!all) {
+          const int TAv = lane < 9 ? trange[lane] : 1, TBv = lane < 9 ? trange[9 + lane] : 0;
+          tmk = (unsigned)__ballot(TAv <= dt && dt <= TBv) & 0x1ffu;
+        }
+        // log2 f by an online log-sum-exp over the live components
+        float mx[4], sm[4];
+        unsigned bits = tmk;
+        const bool single = __builtin_popcount(tmk) == 1;
+        {
+          const int k = bits ? __builtin_ctz(bits) : 0;
+          bits &= bits - 1u;
+          const float mk = comp[(3 * k) * 16 + i16], kk = comp[(3 * k + 1) * 16 + i16];
+          const float wk = tmk ? comp[(3 * k + 2) * 16 + i16] : -INFINITY;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float e = (float)(dbase + q) - mk;
+            mx[q] = fmaf(-e * e, kk, wk);
+            sm[q] = 1.f;
+          }
+        }
+        while (bits) {
+          const int k = __builtin_ctz(bits);
+          bits &= bits - 1u;
+          const float mk = comp[(3 * k) * 16 + i16], kk = comp[(3 * k + 1) * 16 + i16];
+          const float wk = comp[(3 * k + 2) * 16 + i16];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float e = (float)(dbase + q) - mk;
+            const float qv = fmaf(-e * e, kk, wk);
+            const float nm = fmaxf(mx[q], qv);
+            const float sa = nm == -INFINITY ? 0.f : fast_exp2(mx[q] - nm);
+            const float sb = nm == -INFINITY ? 0.f : fast_exp2(qv - nm);
+            sm[q] = fmaf(sm[q], sa, sb);
+            mx[q] = nm;
+          }
+        }
+        float Lq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float lp = (single || mx[q] == -INFINITY) ? mx[q] : mx[q] + fast_log2(sm[q]);
+          Lq[q] = (L.valid && dbase + q <= dhi) ? fmaf(acc[q], cs2, lp) : -INFINITY;
+        }
+        float mt = Lq[0];
+        int qt = 0;
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+          if (Lq[q] > mt) {
+            mt = Lq[q];
+            qt = q;
+          }
+        if (mt > mo.R) {
+          const float sc = fast_exp2(mo.R - mt);
+          const float dnew = (float)(dbase + qt);
+          const float delta = mo.ref - dnew;
+          mo.S0 *= sc;
+          mo.S1 *= sc;
+          mo.S2 *= sc;
+          mo.S2 = fmaf(delta, fmaf(2.f, mo.S1, delta * mo.S0), mo.S2);
+          mo.S1 = fmaf(delta, mo.S0, mo.S1);
+          mo.R = mt;
+          mo.ref = dnew;
+        }
+        if (mt > -INFINITY) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float wq = fast_exp2(Lq[q] - mo.R);
+            const float e = (float)(dbase + q) - mo.ref;
+            mo.S0 += wq;
+            mo.S1 = fmaf(e, wq, mo.S1);
+            mo.S2 = fmaf(e * e, wq, mo.S2);
+          }
+        }
+      };
+
+      // photon count by fp32 dot products with ones (exact integer sums),
+      // count validation by the packed maximum of the raw fp16 bits
+      float Kv = 0.f;
+      ushort2 vmax = {0, 0};
+      auto account = [&](half8 v) __attribute__((always_inline)) {
+        const ushort8 u = __builtin_bit_cast(ushort8, v);
+        const ushort2 m01 = __builtin_elementwise_max(ushort2{u[0], u[1]}, ushort2{u[2], u[3]});
+        const ushort2 m23 = __builtin_elementwise_max(ushort2{u[4], u[5]}, ushort2{u[6], u[7]});
+        vmax = __builtin_elementwise_max(vmax, __builtin_elementwise_max(m01, m23));
+        const half2 one2 = {(_Float16)1.f, (_Float16)1.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Kv = __builtin_amdgcn_fdot2(half2{v[2 * s], v[2 * s + 1]}, one2, Kv, false);
+      };
+      for (int m0 = mb; m0 < me; m0 += RING) {
+#pragma unroll
+        for (int u = 0; u < RING; ++u) {
+          const int m = m0 + u;
+          ring[(u + RING - 1) % RING] = fetch(G.kbA0 + m + RING - 1);
+          if (m < me) {
+            half8 blk[NBP];
+#pragma unroll
+            for (int b = 0; b < NBP; ++b) blk[b] = ring[(u + b) % RING];
+            if constexpr (!kMfma) {
+              wave_sync();
+#pragma unroll
+              for (int b = 0; b < NBP; ++b) ring_store(ring_lds, i16, g, G.kbA0 + m + b, blk[b]);
+              wave_sync();
+            }
+            // every block of the band counted once: the first NBP - 1 with
+            // pair 0, then the last block of each pair
+            if (m == 0) {
+#pragma unroll
+              for (int b = 0; b < NBP - 1; ++b) account(blk[b]);
+            }
+            account(blk[NBP - 1]);
+            // cost of both tiles: the fp16-hi contraction (A operands in
+            // registers) on every pair, the low part only where the pair is
+            // evaluated
+            floatx4 a0, a1;
+            if constexpr (kMfma) {
+              a0 = floatx4{0.f, 0.f, 0.f, 0.f};
+              a1 = a0;
+#pragma unroll
+              for (int b = 0; b < NBP; ++b) {
+                a0 = mfma16(Ahi[0][b], blk[b], a0);
+                a1 = mfma16(Ahi[1][b], blk[b], a1);
+              }
+            } else {
+              a0 = valu_tile(M, ring_lds, i16, g, m, 0);
+              a1 = valu_tile(M, ring_lds, i16, g, m, 1);
+            }
+            // a pixel whose cost in this pair may exceed its margin needs the
+            // pair evaluated with every component (the cost is >= 0: compare
+            // bits); the fp16-hi cost is widened by its rounding (2^-11 per
+            // tap and below 2^-25 absolute per subnormal tap, times counts <=
+            // 2048 and at most 256 taps)
+            const unsigned pm = __builtin_elementwise_max(
+                __builtin_elementwise_max(
+                    __builtin_elementwise_max(__float_as_uint(a0[0]), __float_as_uint(a0[1])),
+                    __builtin_elementwise_max(__float_as_uint(a0[2]), __float_as_uint(a0[3]))),
+                __builtin_elementwise_max(
+                    __builtin_elementwise_max(__float_as_uint(a1[0]), __float_as_uint(a1[1])),
+                    __builtin_elementwise_max(__float_as_uint(a1[2]), __float_as_uint(a1[3]))));
+            const float pub = kSplit ? fmaf(__uint_as_float(pm), 1.0f + 0x1p-9f, kHiSlack) * cs2
+                                     : __uint_as_float(pm) * cs2;  // other engines: the cost itself
+            const bool all = __any(L.valid && pub > Lam);
+            if (all || is_cand(B.pmask, m)) {
+              if constexpr (kSplit) {
+                floatx4 l0 = {0.f, 0.f, 0.f, 0.f}, l1 = l0;
+#pragma unroll
+                for (int b = 0; b < NBP; ++b) {
+                  l0 = mfma16(a_op(sA, NBP, 1, 0, b, lane), blk[b], l0);
+                  l1 = mfma16(a_op(sA, NBP, 1, 1, b, lane), blk[b], l1);
+                }
+                a0 = a0 + l0;
+                a1 = a1 + l1;
+              }
+              for (int tau = 0; tau < 2; ++tau)
+                if (all || is_cand(B.tmask, 2 * m + tau)) tile_epi(tau ? a1 : a0, 2 * m + tau, all);
+            }
+          }
+        }
+      }
+      if (first) {
+        // blocks of [0, T) that no depth window reaches still hold photons
+        for (int kb = 0; kb < G.nkb; ++kb) {
+          if (kb >= G.kbA0 && kb <= G.kb_last) continue;
+          account(load_block(M, L, g, kb));
+        }
+      }
+      // > 2048 or negative
+      const unsigned bad = (vmax[0] > 0x6800u || vmax[1] > 0x6800u) ? kErrOverflow : 0u;
+      if (bad) atomicOr(M.err, bad);
+      const float K = group_sum<16, 32>(Kv);
+      lane_merge(mo);
+      if (g == 0) {
+        if (c < 0) {
+          float* own = block_lds(G, wown).halo;  // the halo is dead once the prior is built
+          put_moments(own, mo, i16);
+          own[80 + i16] = K;
+        } else {
+          put_moments(S.slot + c * 80, mo, i16);
+          atomicAdd(&S.K[i16], (unsigned)K);
+        }
+      }
+      first = false;
+    }
+    if (!helping) {
+      helping = true;
+      bool join = shared;
+      if (wave != 0) {
+        // wait (bounded) for wavefront 0 to publish; a wavefront that gives
+        // up leaves the chunks to the others, which take all of them
+        bool pub = false;
+        for (int n = 0; n < (1 << 20) && !pub; ++n) {
+          pub = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&S.ctl[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0u;
+          if (!pub) __builtin_amdgcn_s_sleep(4);
+        }
+        join = pub && __builtin_amdgcn_readfirstlane(S.ctl[1]) != 0u;
+        if (join) {
+          L = lane_pixel(M, G, io.hist, io.faulty, blockIdx.x, i16, g);
+          B = block_lds(G, smem + G.lds_fixed);
+          Lam = S.lam[i16];
+          wave_live = __builtin_amdgcn_readfirstlane(S.ctl[3]);
+        }
+      }
+      if (!join) break;
+    }
+    int cv = 0;
+    if (lane == 0) cv = (int)atomicAdd(&S.ctl[2], 1u);
+    c = __shfl(cv, 0);
+    if (c >= G.nchunks) break;
+    mb = c * G.chunk;
+    me = mb + G.chunk < G.npairs ? mb + G.chunk : G.npairs;
+    kb_end = G.kbA0 + me + NBP - 2;
+    have = true;
+  }
+  __syncthreads();
+  if (active) {
+    Moments mo;
+    float K;
+    if (wave == 0 && shared) {
+      mo = Moments{-INFINITY, 0.f, 0.f, 0.f, 0.f};
+      for (int k = 0; k < G.nchunks; ++k) merge_moments(mo, get_moments(S.slot + k * 80, i16));
+      K = (float)S.K[i16];
+    } else {
+      const float* own = block_lds(G, wown).halo;
+      mo = get_moments(own, i16);
+      K = own[80 + i16];
+    }
+    const LanePix Lo = lane_pixel(M, G, io.hist, io.faulty, idx, i16, g);
+    step_finish<kEng, NBP>(M, io, Lo, sh_irf, mo, K, lane);
+  }
 }
 
 // LDS of the workgroup: irf and irf^beta (fp32), the A operands, then each
@@ -865,43 +880,21 @@ __device__ __forceinline__ void tile_prologue(const DevModel& M, const TileGeom&
   __syncthreads();
 }
 
-// One launch: workgroups alternate between the two roles while both have
-// work left. Resolve workgroup j takes blocks w * nr + j (w = its
-// wavefronts); bound workgroup j's wavefront w takes blocks 4 j + w + 4 nb k.
+// One frame: wavefront w of workgroup j takes block w * gridDim.x + j, so
+// the border blocks (first in block order) fall on wavefront 0 of distinct
+// workgroups and each can be shared by its workgroup.
 template <int kEng, int NBP>
-__global__ void __launch_bounds__(256, NBP <= 3 ? 4 : 2) k_tile(DevModel M, TileGeom G, TileJob J) {
+__global__ void __launch_bounds__(256, NBP <= 3 ? 4 : 2) k_tile_step(DevModel M, TileGeom G,
+                                                                      StepIO io) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (threadIdx.x == 0) reinterpret_cast<unsigned*>(smem + G.off_share)[0] = 0u;
   tile_prologue<kEng, NBP>(M, G, smem);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int idx = wave * (int)gridDim.x + (int)blockIdx.x;
   const float* sh_irf = reinterpret_cast<const float*>(smem);
   const float* sh_h = sh_irf + M.W;
   const half8* sA = reinterpret_cast<const half8*>(smem + G.lds_a);
-  unsigned char* wbase = smem + G.lds_fixed + wave * G.lds_per_wave;
-
-  const int i = blockIdx.x, both = J.nr < J.nb ? J.nr : J.nb;
-  bool resolve;
-  int j;
-  if (i < 2 * both) {
-    resolve = (i & 1) == 0;
-    j = i >> 1;
-  } else {
-    resolve = J.nr > J.nb;
-    j = i - both;
-  }
-  if (resolve) {
-    resolve_group<kEng, NBP>(M, G, J, j, sA, sh_irf, sh_h, smem, wave, lane);
-  } else {
-    half8 Ahi[2][NBP];
-    if constexpr (kEng != kEngValu) {
-#pragma unroll
-      for (int tau = 0; tau < 2; ++tau)
-#pragma unroll
-        for (int b = 0; b < NBP; ++b) Ahi[tau][b] = a_op(sA, NBP, 0, tau, b, lane);
-    }
-    _Float16* ring_lds = reinterpret_cast<_Float16*>(wbase + G.off_ring);
-    for (int idx = 4 * j + wave; idx < G.nblk; idx += 4 * J.nb)
-      bound_block<kEng, NBP>(M, G, J.bhist, J.bfaulty, J.bbound, idx, Ahi, ring_lds, lane);
-  }
+  step_wave<kEng, NBP>(M, G, io, idx, wave, sA, sh_irf, sh_h, smem, lane);
 }
 
 // a3 alone: the exact cost of every grid depth written out.
@@ -964,49 +957,52 @@ bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
   G.nblk = ((M.rows + 3) / 4) * G.nbc;
   // byte offsets inside one 4x4 block's rows must fit the 32-bit buffer offset
   if ((long long)(3 * M.cols + 4) * M.T * 2 >= 0x7fffffffLL) return false;
-  // workgroup: irf and irf^beta (fp32), the A operands, the resolve role's
-  // shared counts and partial moments; then one region per wavefront: masks,
-  // component tile ranges, halo, components and (VALU engine) the ring
+  // workgroup: irf and irf^beta (fp32) and the A operands; then one region
+  // per wavefront: masks, component tile ranges, halo, components and (VALU
+  // engine) the ring
   G.lds_a = ((8 * M.W + 15) / 16) * 16;
-  G.lds_share = G.lds_a + (engine == kEngValu ? 0 : 2 * 2 * G.nbp * 64 * 16);
-  G.lds_fixed = G.lds_share + 16 + 4 * 5 * 64 * 4;
+  G.lds_fixed = G.lds_a + (engine == kEngValu ? 0 : 2 * 2 * G.nbp * 64 * 16);
   G.off_trange = ((4 * (G.mask_words + G.pair_words + G.need_words) + 15) / 16) * 16;
   G.off_halo = G.off_trange + 80;
   G.off_comp = G.off_halo + kHaloBytes;
   G.off_ring = G.off_comp + kCompBytes;
   G.lds_per_wave = G.off_ring + (engine == kEngValu ? 16 * kRingT * 2 : 0);
+  G.off_share = G.lds_fixed + 4 * G.lds_per_wave;
+  G.lds_total = G.off_share + kShareBytes;
+  // chunks of at least 8 pairs: the ring's first RING - 1 blocks are loaded
+  // before the block's chunking is known and must lie in the band of its
+  // first chunk (RING - NBP <= 6)
+  G.chunk = (G.npairs + kMaxChunks - 1) / kMaxChunks;
+  if (G.chunk < 8) G.chunk = 8;
+  G.nchunks = (G.npairs + G.chunk - 1) / G.chunk;
   if (engine == kEngValu && 32 * G.nbp > kRingT) return false;
-  return (size_t)G.lds_fixed + 4 * (size_t)G.lds_per_wave <= 65536;
+  return G.lds_total <= 65536;
 }
 
-int tile_workgroups(const DevModel& M) {
-  const int nblk = ((M.rows + 3) / 4) * ((M.cols + 3) / 4);
-  return (nblk + 3) / 4;
-}
 
 template <int kEng>
-static hipError_t launch_eng(const DevModel& M, const TileGeom& G, const TileJob& J, hipStream_t s) {
-  const int both = J.nr < J.nb ? J.nr : J.nb;
-  const dim3 grid(J.nr + J.nb - both + both), block(256);
-  if (grid.x == 0) return hipSuccess;
-  const size_t lds = G.lds_fixed + 4 * (size_t)G.lds_per_wave;
+static hipError_t launch_step_eng(const DevModel& M, const TileGeom& G, const StepIO& io,
+                                  hipStream_t s) {
+  const size_t lds = G.lds_total;
+  const dim3 grid((G.nblk + 3) / 4), block(256);
+  if (G.nblk < 1) return hipErrorInvalidValue;
   switch (G.nbp) {
-    case 2: hipLaunchKernelGGL((k_tile<kEng, 2>), grid, block, lds, s, M, G, J); break;
-    case 3: hipLaunchKernelGGL((k_tile<kEng, 3>), grid, block, lds, s, M, G, J); break;
-    case 4: hipLaunchKernelGGL((k_tile<kEng, 4>), grid, block, lds, s, M, G, J); break;
-    case 5: hipLaunchKernelGGL((k_tile<kEng, 5>), grid, block, lds, s, M, G, J); break;
+    case 2: hipLaunchKernelGGL((k_tile_step<kEng, 2>), grid, block, lds, s, M, G, io); break;
+    case 3: hipLaunchKernelGGL((k_tile_step<kEng, 3>), grid, block, lds, s, M, G, io); break;
+    case 4: hipLaunchKernelGGL((k_tile_step<kEng, 4>), grid, block, lds, s, M, G, io); break;
+    case 5: hipLaunchKernelGGL((k_tile_step<kEng, 5>), grid, block, lds, s, M, G, io); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_tile(const DevModel& M, int engine, const TileJob& job, hipStream_t s) {
+hipError_t launch_step_tile(const DevModel& M, int engine, const StepIO& io, hipStream_t s) {
   TileGeom G;
   if (!tile_geometry(M, engine, G)) return hipErrorInvalidValue;
   switch (engine) {
-    case kEngValu: return launch_eng<kEngValu>(M, G, job, s);
-    case kEngMfma16: return launch_eng<kEngMfma16>(M, G, job, s);
-    case kEngMfma16x2: return launch_eng<kEngMfma16x2>(M, G, job, s);
+    case kEngValu: return launch_step_eng<kEngValu>(M, G, io, s);
+    case kEngMfma16: return launch_step_eng<kEngMfma16>(M, G, io, s);
+    case kEngMfma16x2: return launch_step_eng<kEngMfma16x2>(M, G, io, s);
   }
   return hipErrorInvalidValue;
 }

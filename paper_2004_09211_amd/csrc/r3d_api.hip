@@ -23,8 +23,6 @@ struct r3d_ctx {
   float* d_irf = nullptr;
   _Float16* d_h16 = nullptr;  // [2*W]: hi then lo
   unsigned* d_err = nullptr;
-  r3d::TileBound* d_bound = nullptr;  // [2*P]: per-pixel cost bounds of two frames
-  int bound_wgs = 0;                   // bound workgroups of a pipelined launch
 };
 
 namespace {
@@ -110,7 +108,6 @@ void free_ctx(r3d_ctx* c) {
   if (c->d_irf) (void)hipFree(c->d_irf);
   if (c->d_h16) (void)hipFree(c->d_h16);
   if (c->d_err) (void)hipFree(c->d_err);
-  if (c->d_bound) (void)hipFree(c->d_bound);
   delete c;
 }
 
@@ -200,24 +197,6 @@ r3d_status r3d_create(const r3d_params* params, r3d_ctx** out) {
     free_ctx(c);
     return R3D_EUNSUPPORTED;
   }
-  if (r3d::tile_supported(m, params->precision)) {
-    // two frames of per-pixel bounds for the histogram path, and the
-    // workgroups that stream bounds in a pipelined launch: two wavefronts
-    // per SIMD, leaving the other slots to the resolving workgroups
-    int ncu = 0;
-    if (hipMalloc(&c->d_bound, 2 * (size_t)m.P * sizeof(r3d::TileBound)) != hipSuccess) {
-      free_ctx(c);
-      return R3D_ENOMEM;
-    }
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) !=
-        hipSuccess) {
-      free_ctx(c);
-      return R3D_EHIP;
-    }
-    // (the fp32 engine's bound pass is vector-ALU bound, so it keeps every
-    // workgroup it can get)
-    c->bound_wgs = params->precision == R3D_FP32 ? (1 << 30) : 2 * (ncu > 0 ? ncu : 1);
-  }
   *out = c;
   return R3D_OK;
 }
@@ -272,22 +251,8 @@ r3d_status r3d_step_hist(r3d_ctx* ctx, const uint16_t* hist, const float* pi_in,
   io.hist = hist;
   const int engine = ctx->prm.precision;  // r3d_precision values are the engine ids
   const hipStream_t s = (hipStream_t)stream;
-  if (ctx->d_bound && ((uintptr_t)hist & 15u) == 0) {
-    // bounds of the frame, then its resolution
-    const int wgs = r3d::tile_workgroups(ctx->dm);
-    r3d::TileJob jb{};
-    jb.bhist = hist;
-    jb.bfaulty = faulty;
-    jb.bbound = ctx->d_bound;
-    jb.nb = wgs;
-    r3d_status st = hip_status(r3d::launch_tile(ctx->dm, engine, jb, s));
-    if (st != R3D_OK) return st;
-    r3d::TileJob jr{};
-    jr.io = io;
-    jr.rbound = ctx->d_bound;
-    jr.nr = wgs;
-    return hip_status(r3d::launch_tile(ctx->dm, engine, jr, s));
-  }
+  if (r3d::tile_supported(ctx->dm, engine) && ((uintptr_t)hist & 15u) == 0)
+    return hip_status(r3d::launch_step_tile(ctx->dm, engine, io, s));
   if (engine != R3D_FP32) return R3D_EUNSUPPORTED;
   return hip_status(r3d::launch_step_plain(ctx->dm, io, true, s));
 }
@@ -302,40 +267,24 @@ r3d_status r3d_run_hist(r3d_ctx* ctx, const uint16_t* const* hist, int32_t nfram
     if (!hist[n]) return R3D_EINVAL;
     if ((uintptr_t)hist[n] & 15u) return R3D_EUNSUPPORTED;
   }
-  if (!ctx->d_bound) return R3D_EUNSUPPORTED;
   const int engine = ctx->prm.precision;
+  if (!r3d::tile_supported(ctx->dm, engine)) return R3D_EUNSUPPORTED;
   const hipStream_t s = (hipStream_t)stream;
   const size_t P = (size_t)ctx->dm.P;
-  const int wgs = r3d::tile_workgroups(ctx->dm);
-  const int nbw = wgs < ctx->bound_wgs ? wgs : ctx->bound_wgs;
-  // launch n resolves frame n - 1 and computes the bounds of frame n; the
-  // bounds alternate between the two halves of the context's buffer
-  for (int n = 0; n <= nframes; ++n) {
-    r3d::TileJob J{};
-    if (n < nframes) {
-      J.bhist = hist[n];
-      J.bfaulty = faulty;
-      J.bbound = ctx->d_bound + (size_t)(n % 2) * P;
-      J.nb = n == 0 ? wgs : nbw;
+  for (int f = 0; f < nframes; ++f) {
+    const size_t o = (size_t)f * P;
+    r3d_out of{};
+    if (out) {
+      of.depth = out->depth ? out->depth + o : nullptr;
+      of.var = out->var ? out->var + o : nullptr;
+      of.intensity = out->intensity ? out->intensity + o : nullptr;
+      of.background = out->background ? out->background + o : nullptr;
+      of.pi0_next = out->pi0_next ? out->pi0_next + o : nullptr;
+      of.argmax = out->argmax ? out->argmax + o : nullptr;
     }
-    if (n > 0) {
-      const int f = n - 1;
-      const size_t o = (size_t)f * P;
-      r3d_out of{};
-      if (out) {
-        of.depth = out->depth ? out->depth + o : nullptr;
-        of.var = out->var ? out->var + o : nullptr;
-        of.intensity = out->intensity ? out->intensity + o : nullptr;
-        of.background = out->background ? out->background + o : nullptr;
-        of.pi0_next = out->pi0_next ? out->pi0_next + o : nullptr;
-        of.argmax = out->argmax ? out->argmax + o : nullptr;
-      }
-      J.io = make_io(pi_in ? pi_in + o : nullptr, faulty, &state[f % 2], &state[(f + 1) % 2], &of);
-      J.io.hist = hist[f];
-      J.rbound = ctx->d_bound + (size_t)(f % 2) * P;
-      J.nr = wgs;
-    }
-    const r3d_status st = hip_status(r3d::launch_tile(ctx->dm, engine, J, s));
+    r3d::StepIO io = make_io(pi_in ? pi_in + o : nullptr, faulty, &state[f % 2], &state[(f + 1) % 2], &of);
+    io.hist = hist[f];
+    const r3d_status st = hip_status(r3d::launch_step_tile(ctx->dm, engine, io, s));
     if (st != R3D_OK) return st;
   }
   return R3D_OK;

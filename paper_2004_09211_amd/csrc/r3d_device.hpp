@@ -69,9 +69,10 @@ struct Comps {
   unsigned live;
 };
 
+// log2(2^a + 2^b) with the hardware exp2 / log2 (about 1 ulp each)
 __device__ __forceinline__ float log2_add(float a, float b) {
   const float mx = fmaxf(a, b), mn = fminf(a, b);
-  return mx + log2f(1.0f + exp2f(mn - mx));
+  return mx + fast_log2(1.0f + fast_exp2(mn - mx));
 }
 
 // merge components with identical (m, V) into the first of them
@@ -119,7 +120,7 @@ __device__ __forceinline__ void build_components_raw(const DevModel& M,
     Vk[k] = V;
     C.m[k] = m;
     C.k2[k] = 0.5f * kLog2e / V;
-    C.w2[k] = M.lognu2[k] - 0.5f * (kLog2TwoPi + log2f(V));
+    C.w2[k] = M.lognu2[k] - 0.5f * (kLog2TwoPi + fast_log2(V));
     C.live |= (C.w2[k] > -INFINITY ? 1u : 0u) << k;
   }
 }
@@ -178,9 +179,9 @@ __device__ __forceinline__ float pi0_next_at(const DevModel& M, const float* __r
     if (rr < 0 || rr >= M.rows || cc < 0 || cc >= M.cols) continue;
     float pk = pi_now_at(pi_in, faulty, rr * M.cols + cc);
     pk = fminf(fmaxf(pk, 1e-6f), 1.0f - 1e-6f);
-    acc += M.nu[k] * logf(pk / (1.0f - pk));
+    acc += M.nu[k] * (fast_log2(pk) - fast_log2(1.0f - pk));  // logit in log2 units
   }
-  return 1.0f / (1.0f + expf(-acc));
+  return fast_rcp(1.0f + fast_exp2(-acc));
 }
 
 // Maximum-likelihood reflectivity r and background b of a detected pixel
@@ -236,7 +237,7 @@ __device__ __forceinline__ void mle_reflectivity(Terms terms, float K, float S, 
     else
       hi = r;
     if (g1 == 0.f) break;
-    const float step = g1 / g2;
+    const float step = g1 * fast_rcp(g2);
     const float tol = 1e-5f * fmaxf(r, 1.0f);
     if (fabsf(step) <= tol) {  // converged: the Newton step is below the noise floor
       r = fminf(fmaxf(r - step, lo), hi);

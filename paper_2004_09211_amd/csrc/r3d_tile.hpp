@@ -8,6 +8,7 @@ namespace r3d {
 
 enum { kEngValu = 0, kEngMfma16 = 1, kEngMfma16x2 = 2 };
 constexpr int kTileMaxNBP = 5;  // 32-bin blocks spanned by a 32-bin pair of depth tiles
+constexpr int kMaxChunks = 16;  // chunks of pairs of a block shared by a workgroup's wavefronts
 
 struct TileGeom {
   int o;           // (d_lo - c) mod 32
@@ -23,34 +24,17 @@ struct TileGeom {
   int nbc;         // 4x4 pixel blocks per block-row
   int nblk;        // 4x4 pixel blocks in the frame
   int lds_a;       // byte offset of the matrix-core A operands
-  int lds_share;   // byte offset of the resolve role's shared counts and partial moments
-  int lds_fixed;   // bytes shared by the workgroup
+  int lds_fixed;   // bytes before the four wavefront regions
   int lds_per_wave, off_trange, off_halo, off_comp, off_ring;  // per-wavefront bytes, offsets
-};
-
-// Per-pixel output of the bound pass: the largest cost over the depth grid
-// (matrix engines: of the fp16-hi contraction, in its raw units) and the
-// photon count K.
-typedef float2 TileBound;
-
-// One launch of the tile kernel: resolve one frame (whose bounds are ready)
-// and/or compute the bounds of another frame. nr / nb are the workgroups of
-// each role (0 = none).
-struct TileJob {
-  StepIO io;                 // resolved frame: histograms, states, outputs
-  const TileBound* rbound;   // its bounds
-  int nr;
-  const uint16_t* bhist;     // frame whose bounds are computed
-  const uint8_t* bfaulty;
-  TileBound* bbound;
-  int nb;
+  int off_share;   // byte offset of the workgroup's shared chunk region
+  int lds_total;   // bytes of LDS of one workgroup
+  int chunk;       // pairs per chunk of a shared block
+  int nchunks;     // ceil(npairs / chunk) <= kMaxChunks
 };
 
 bool tile_geometry(const DevModel& M, int engine, TileGeom& G);
 bool tile_supported(const DevModel& M, int engine);
-hipError_t launch_tile(const DevModel& M, int engine, const TileJob& job, hipStream_t s);
-// workgroups for a bound-only or resolve-only launch of the frame
-int tile_workgroups(const DevModel& M);
+hipError_t launch_step_tile(const DevModel& M, int engine, const StepIO& io, hipStream_t s);
 hipError_t launch_cost_tile(const DevModel& M, int engine, const uint16_t* hist, int npix,
                             float* ell, hipStream_t s);
 
