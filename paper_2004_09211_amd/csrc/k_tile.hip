@@ -108,6 +108,7 @@ struct LanePix {
   bool valid, faulty, has_data;
   __amdgpu_buffer_rsrc_t hbuf;
   unsigned off;
+  unsigned klim;  // blocks kb < klim hold this lane's 8 bins (0 without data)
 };
 
 __device__ __forceinline__ LanePix lane_pixel(const DevModel& M, const TileGeom& G,
@@ -129,13 +130,13 @@ __device__ __forceinline__ LanePix lane_pixel(const DevModel& M, const TileGeom&
                                              (int)(rec < 0x7fffffffLL ? rec : 0x7fffffffLL),
                                              kBufWord3);
   L.off = L.has_data ? (unsigned)(((L.p - p0) * M.T + 8 * g) * 2) : kOob;
+  L.klim = L.has_data ? (unsigned)((M.T - 8 * g + 31) / 32) : 0u;
   return L;
 }
 
 // Block kb (bins 32 kb .. 32 kb + 31) of the lane's pixel, 8 bins per lane.
 __device__ __forceinline__ half8 load_block(const DevModel& M, const LanePix& L, int g, int kb) {
-  const bool in = kb >= 0 && 32 * kb + 8 * g < M.T && L.off != kOob;
-  const unsigned off = in ? L.off + 64u * (unsigned)kb : kOob;
+  const unsigned off = (unsigned)kb < L.klim ? L.off + 64u * (unsigned)kb : kOob;
   return __builtin_bit_cast(half8, __builtin_amdgcn_raw_buffer_load_b128(L.hbuf, off, 0, 0));
 }
 
@@ -603,6 +604,17 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   auto is_cand = [&](const unsigned* mk, int i) __attribute__((always_inline)) -> bool {
     return (__builtin_amdgcn_readfirstlane(mk[i >> 5]) >> (i & 31)) & 1u;
   };
+  // the margin test on the raw cost bits: a pair is evaluated for the lane's
+  // pixel when the largest raw cost of its 8 depths reaches thr, the margin
+  // taken back through the fp16-hi widening (the split engine) and lowered
+  // by 2^-20 relative so that the rounding of this conversion only adds
+  // evaluations; lanes without a pixel never reach it
+  auto margin_bits = [&](float lam) __attribute__((always_inline)) -> unsigned {
+    float thr = kSplit ? (lam / cs2 - kHiSlack) * (1.0f / (1.0f + 0x1p-9f)) : lam / cs2;
+    thr *= 1.0f - 0x1p-20f;
+    return !L.valid ? 0x7f800000u : (thr > 0.f ? __float_as_uint(thr) : 0u);
+  };
+  unsigned thr = margin_bits(Lam);
 
   // first: the task is the wavefront's own block, whose first ring blocks
   // are already loaded (a wavefront without a block starts with a chunk)
@@ -707,6 +719,12 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
         for (int s = 0; s < 4; ++s) Kv = __builtin_amdgcn_fdot2(half2{v[2 * s], v[2 * s + 1]}, one2, Kv, false);
       };
       for (int m0 = mb; m0 < me; m0 += RING) {
+        // candidate-pair bits of pairs m0 .. m0 + RING - 1 (< 41 bits past
+        // pbase)
+        const int pbase = m0 & ~31;
+        const unsigned long long pbits =
+            (unsigned long long)__builtin_amdgcn_readfirstlane(B.pmask[pbase >> 5]) |
+            ((unsigned long long)__builtin_amdgcn_readfirstlane(B.pmask[(pbase >> 5) + 1]) << 32);
 #pragma unroll
         for (int u = 0; u < RING; ++u) {
           const int m = m0 + u;
@@ -756,10 +774,8 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
                 __builtin_elementwise_max(
                     __builtin_elementwise_max(__float_as_uint(a1[0]), __float_as_uint(a1[1])),
                     __builtin_elementwise_max(__float_as_uint(a1[2]), __float_as_uint(a1[3]))));
-            const float pub = kSplit ? fmaf(__uint_as_float(pm), 1.0f + 0x1p-9f, kHiSlack) * cs2
-                                     : __uint_as_float(pm) * cs2;  // other engines: the cost itself
-            const bool all = __any(L.valid && pub > Lam);
-            if (all || is_cand(B.pmask, m)) {
+            const bool all = __any(pm >= thr);
+            if (all || ((pbits >> (m - pbase)) & 1u)) {
               if constexpr (kSplit) {
                 floatx4 l0 = {0.f, 0.f, 0.f, 0.f}, l1 = l0;
 #pragma unroll
@@ -816,7 +832,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
         if (join) {
           L = lane_pixel(M, G, io.hist, io.faulty, blockIdx.x, i16, g);
           B = block_lds(G, smem + G.lds_fixed);
-          Lam = S.lam[i16];
+          thr = margin_bits(S.lam[i16]);
           wave_live = __builtin_amdgcn_readfirstlane(S.ctl[3]);
         }
       }
@@ -824,7 +840,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
     }
     int cv = 0;
     if (lane == 0) cv = (int)atomicAdd(&S.ctl[2], 1u);
-    c = __shfl(cv, 0);
+    c = __builtin_amdgcn_readfirstlane(cv);
     if (c >= G.nchunks) break;
     mb = c * G.chunk;
     me = mb + G.chunk < G.npairs ? mb + G.chunk : G.npairs;
@@ -889,7 +905,9 @@ __global__ void __launch_bounds__(256, NBP <= 3 ? 4 : 2) k_tile_step(DevModel M,
   extern __shared__ __align__(16) unsigned char smem[];
   if (threadIdx.x == 0) reinterpret_cast<unsigned*>(smem + G.off_share)[0] = 0u;
   tile_prologue<kEng, NBP>(M, G, smem);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wavefront index is uniform: say so, so that everything derived from
+  // it (the block, its buffer descriptor, the task switches) stays scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int idx = wave * (int)gridDim.x + (int)blockIdx.x;
   const float* sh_irf = reinterpret_cast<const float*>(smem);
   const float* sh_h = sh_irf + M.W;
