@@ -107,13 +107,22 @@ struct LanePix {
   int br, bc, p;
   bool valid, faulty, has_data;
   __amdgpu_buffer_rsrc_t hbuf;
-  unsigned off;
-  unsigned klim;  // blocks kb < klim hold this lane's 8 bins (0 without data)
+  unsigned off_row;  // byte offset of the lane's 8 bins of block 0
+  unsigned off;      // off_row, or past the records without data
+  unsigned klim;     // blocks kb < klim hold this lane's 8 bins (0 without data)
 };
 
-__device__ __forceinline__ LanePix lane_pixel(const DevModel& M, const TileGeom& G,
-                                              const uint16_t* hist, const uint8_t* faulty,
-                                              int idx, int i16, int g) {
+// Mark the lane's pixel faulty (or not): a faulty pixel's photons are ignored.
+__device__ __forceinline__ void lane_set_faulty(const DevModel& M, LanePix& L, int g, bool f) {
+  L.faulty = L.valid && f;
+  L.has_data = L.valid && !f;
+  L.off = L.has_data ? L.off_row : kOob;
+  L.klim = L.has_data ? (unsigned)((M.T - 8 * g + 31) / 32) : 0u;
+}
+
+// The lane's pixel without its faulty flag (taken as not faulty).
+__device__ __forceinline__ LanePix lane_pixel_nf(const DevModel& M, const TileGeom& G,
+                                                 const uint16_t* hist, int idx, int i16, int g) {
   LanePix L;
   int br, bc;
   block_of(idx, G.nblk / G.nbc, G.nbc, br, bc);
@@ -122,15 +131,21 @@ __device__ __forceinline__ LanePix lane_pixel(const DevModel& M, const TileGeom&
   const int pr = 4 * L.br + (i16 >> 2), pc = 4 * L.bc + (i16 & 3);
   L.valid = pr < M.rows && pc < M.cols && pr * M.cols + pc < M.P;
   L.p = L.valid ? pr * M.cols + pc : 0;
-  L.faulty = L.valid && faulty && faulty[L.p];
-  L.has_data = L.valid && !L.faulty;
   const int p0 = __builtin_amdgcn_readfirstlane((4 * L.br) * M.cols + 4 * L.bc);
   const long long rec = (long long)(M.P - p0) * M.T * 2;
   L.hbuf = __builtin_amdgcn_make_buffer_rsrc((void*)(hist + (size_t)p0 * M.T), (short)0,
                                              (int)(rec < 0x7fffffffLL ? rec : 0x7fffffffLL),
                                              kBufWord3);
-  L.off = L.has_data ? (unsigned)(((L.p - p0) * M.T + 8 * g) * 2) : kOob;
-  L.klim = L.has_data ? (unsigned)((M.T - 8 * g + 31) / 32) : 0u;
+  L.off_row = (unsigned)(((L.p - p0) * M.T + 8 * g) * 2);
+  lane_set_faulty(M, L, g, false);
+  return L;
+}
+
+__device__ __forceinline__ LanePix lane_pixel(const DevModel& M, const TileGeom& G,
+                                              const uint16_t* hist, const uint8_t* faulty,
+                                              int idx, int i16, int g) {
+  LanePix L = lane_pixel_nf(M, G, hist, idx, i16, g);
+  lane_set_faulty(M, L, g, L.valid && faulty && faulty[L.p]);
   return L;
 }
 
@@ -138,6 +153,16 @@ __device__ __forceinline__ LanePix lane_pixel(const DevModel& M, const TileGeom&
 __device__ __forceinline__ half8 load_block(const DevModel& M, const LanePix& L, int g, int kb) {
   const unsigned off = (unsigned)kb < L.klim ? L.off + 64u * (unsigned)kb : kOob;
   return __builtin_bit_cast(half8, __builtin_amdgcn_raw_buffer_load_b128(L.hbuf, off, 0, 0));
+}
+
+// Bin t of the lane's pixel as a float; zero for t outside [0, T) or a lane
+// without data (the load is issued unconditionally, so that a run of them
+// is in flight at once).
+__device__ __forceinline__ float load_bin(const DevModel& M, const LanePix& L, int g, int t, bool use) {
+  const unsigned off = (use && (unsigned)t < (unsigned)M.T && L.off != kOob)
+                           ? L.off + 2u * (unsigned)(t - 8 * g) : kOob;
+  const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(L.hbuf, off, 0, 0);
+  return (float)__builtin_bit_cast(_Float16, b);
 }
 
 // A load past every record: zeros, no memory traffic (keeps the count of
@@ -298,40 +323,41 @@ __device__ __forceinline__ BlockLds block_lds(const TileGeom& G, unsigned char* 
 
 // Prior, reference cost and candidate tiles of block idx into its LDS
 // region; returns the lane's cost margin Lambda (log2 units) and the
-// components live for some pixel (wave-uniform).
-template <int kEng, int NBP>
+// components live for some pixel (wave-uniform). after_gather() is called
+// once the state and reference-cost loads are issued (the caller's first
+// histogram loads then queue behind them).
+template <int kEng, int NBP, typename AfterGather>
 __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, const StepIO& io,
-                                          const LanePix& L, const float* sh_h, const BlockLds& B,
-                                          int lane, float& Lam, unsigned& wave_live) {
+                                          LanePix& L, const float* sh_h, const BlockLds& B,
+                                          int lane, float& Lam, unsigned& wave_live,
+                                          AfterGather&& after_gather) {
   constexpr bool kMfma = kEng != kEngValu;
   constexpr bool kSplit = kEng == kEngMfma16x2;
   // taps per lane (j = g + 4 u): W <= 32 NBP - 30 by construction of NBP, so u < 8 NBP - 7
   constexpr int U = 8 * NBP - 7;
   const int i16 = lane & 15, g = lane >> 4;
   const int dhi = M.d_lo + M.D - 1;
-  const uint16_t* row = io.hist + (size_t)L.p * M.T;
 
-  // previous states of the block's 6x6 halo
-  if (lane < 36) {
-    const int hr = 4 * L.br - 1 + lane / 6, hc = 4 * L.bc - 1 + lane % 6;
-    float hm = 0.f, hv = 1.f, hp = -1.f;
-    if (hr >= 0 && hr < M.rows && hc >= 0 && hc < M.cols) {
-      const int q = hr * M.cols + hc;
-      hm = io.pm[q];
-      hv = io.pv[q];
-      hp = io.ppi[q];
-    }
-    B.halo[lane] = hm;
-    B.halo[36 + lane] = hv;
-    B.halo[72 + lane] = hp;
+  // One round of independent loads (unconditional, from clamped indices, so
+  // that they are all in flight together): the pixel's own state and faulty
+  // flag, and the previous states of the block's 6x6 halo.
+  const float pm_own = io.pm[L.p], ppi_own = io.ppi[L.p];
+  const bool f_own = io.faulty ? io.faulty[L.p] != 0 : false;
+  const int hl = lane < 36 ? lane : 0;
+  const int hr = 4 * L.br - 1 + hl / 6, hc = 4 * L.bc - 1 + hl % 6;
+  const bool hin = hr >= 0 && hr < M.rows && hc >= 0 && hc < M.cols;
+  const int hq = hin ? hr * M.cols + hc : 0;
+  float hm = io.pm[hq], hv = io.pv[hq], hp = io.ppi[hq];
+  // keep these loads ahead of the histogram loads issued below
+  asm volatile("" ::: "memory");
+  if (!hin) {
+    hm = 0.f;
+    hv = 1.f;
+    hp = -1.f;
   }
-  // reference depth: the rounded mean of the pixel's own prior component,
-  // read directly so that the gather of its cost starts at once
-  float mown = M.m_flat;
-  if (L.valid) {
-    const float pm = io.pm[L.p];
-    mown = io.ppi[L.p] > 0.5f ? pm : M.m_flat;
-  }
+  lane_set_faulty(M, L, g, f_own);
+  // reference depth: the rounded mean of the pixel's own prior component
+  const float mown = (L.valid && ppi_own > 0.5f) ? pm_own : M.m_flat;
   const int dref = (int)fminf(fmaxf(rintf(mown), (float)M.d_lo), (float)dhi);
   // exact cost at d_ref by an fp32 gather (the lane takes taps j = g + 4 u)
   float zr[U];
@@ -339,7 +365,13 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
   for (int u = 0; u < U; ++u) {
     const int j = g + 4 * u;
     const int t = dref - M.c + j;
-    zr[u] = (L.has_data && j < M.W && t >= 0 && t < M.T) ? half_bits_to_float(row[t]) : 0.f;
+    zr[u] = load_bin(M, L, g, t, j < M.W);
+  }
+  after_gather();
+  if (lane < 36) {
+    B.halo[lane] = hm;
+    B.halo[36 + lane] = hv;
+    B.halo[72 + lane] = hp;
   }
   wave_sync();
 
@@ -431,7 +463,6 @@ __device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io,
                                             const float* sh_irf, Moments mo, float K, int lane) {
   constexpr int U = 8 * NBP - 7;  // taps per lane, as in step_prep
   const int g = lane >> 4;
-  const uint16_t* row = io.hist + (size_t)L.p * M.T;
   const float mu = mo.S1 / mo.S0;
   const int dstar = (int)mo.ref;
   const float mean = mo.ref + mu;
@@ -450,7 +481,7 @@ __device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io,
     const int j = g + 4 * u;
     const int t = dstar - M.c + j;
     const bool in = j < M.W && t >= 0 && t < M.T;
-    wz[u] = (in && L.has_data) ? half_bits_to_float(row[t]) : 0.f;
+    wz[u] = load_bin(M, L, g, t, in);
     ws[u] = in ? sh_irf[j] : 0.f;
     S += ws[u];
     Kw += wz[u];
@@ -550,18 +581,14 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
 
   // current task: pairs [mb, me) of the block of L and B; c = its chunk, or
   // -1 for a whole block
-  LanePix L = lane_pixel(M, G, io.hist, io.faulty, active ? idx : 0, i16, g);
+  // (the faulty flag of the own block is read with the prior's loads)
+  LanePix L = lane_pixel_nf(M, G, io.hist, active ? idx : 0, i16, g);
   BlockLds B = block_lds(G, wown);
   int mb = 0, me = G.npairs, c = -1, kb_end = G.kb_last;
   auto fetch = [&](int kb) __attribute__((always_inline)) -> half8 {
     return load_block(M, L, g, kb <= kb_end ? kb : -1);
   };
-  // the first blocks are in flight while the prior is prepared
   half8 ring[RING];
-  if (active) {
-#pragma unroll
-    for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + x);
-  }
   half8 Ahi[2][NBP];
   if constexpr (kMfma) {
 #pragma unroll
@@ -571,7 +598,13 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   }
   float Lam = 0.f;
   unsigned wave_live = 0u;
-  if (active) step_prep<kEng, NBP>(M, G, io, L, sh_h, B, lane, Lam, wave_live);
+  // the first blocks are in flight while the prior is prepared
+  if (active)
+    step_prep<kEng, NBP>(M, G, io, L, sh_h, B, lane, Lam, wave_live, [&]() __attribute__((always_inline)) {
+#pragma unroll
+      for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + x);
+    });
+  const bool own_faulty = L.faulty;
   bool shared = false;
   if (wave == 0) {
     // a block with candidate tiles on most pairs (a frame border, a flat
@@ -860,7 +893,8 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
       mo = get_moments(own, i16);
       K = own[80 + i16];
     }
-    const LanePix Lo = lane_pixel(M, G, io.hist, io.faulty, idx, i16, g);
+    LanePix Lo = lane_pixel_nf(M, G, io.hist, idx, i16, g);
+    lane_set_faulty(M, Lo, g, own_faulty);
     step_finish<kEng, NBP>(M, io, Lo, sh_irf, mo, K, lane);
   }
 }
@@ -896,7 +930,7 @@ __device__ __forceinline__ void tile_prologue(const DevModel& M, const TileGeom&
   __syncthreads();
 }
 
-// One frame: wavefront w of workgroup j takes block w * gridDim.x + j, so
+// One frame: wavefront w of workgroup j takes block w * (workgroups) + j, so
 // the border blocks (first in block order) fall on wavefront 0 of distinct
 // workgroups and each can be shared by its workgroup.
 template <int kEng, int NBP>
@@ -908,7 +942,7 @@ __global__ void __launch_bounds__(256, NBP <= 3 ? 4 : 2) k_tile_step(DevModel M,
   // the wavefront index is uniform: say so, so that everything derived from
   // it (the block, its buffer descriptor, the task switches) stays scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int idx = wave * (int)gridDim.x + (int)blockIdx.x;
+  const int idx = wave * ((G.nblk + 3) >> 2) + (int)blockIdx.x;  // the grid has (nblk + 3) / 4 workgroups
   const float* sh_irf = reinterpret_cast<const float*>(smem);
   const float* sh_h = sh_irf + M.W;
   const half8* sA = reinterpret_cast<const half8*>(smem + G.lds_a);
