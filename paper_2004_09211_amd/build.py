@@ -25,6 +25,13 @@ CXXFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,
 ]
+# per-file flags: the tile kernels take block-wide minima, maxima and bit
+# masks with LDS atomics from up to 16 lanes on one address; the compiler's
+# atomic optimizer turns each into a loop over the active lanes, far slower
+# than the LDS unit serialising them
+FILE_FLAGS = {
+    "k_tile.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+}
 
 
 def hipcc() -> str:
@@ -36,7 +43,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *CXXFLAGS, "-c", src, "-o", obj]
+    cmd = [hipcc(), *CXXFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
