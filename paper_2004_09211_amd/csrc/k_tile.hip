@@ -50,7 +50,7 @@ constexpr float kLiveGap = 40.f;        // log2 units
 constexpr unsigned kOob = 0x80000000u;  // buffer offset past every record: loads return zeros
 constexpr int kBufWord3 = 0x00020000;   // raw buffer descriptor, 32-bit data format
 constexpr int kHaloBytes = 448;         // 6x6 halo of (m, v, pi), 108 floats
-constexpr int kCompBytes = 9 * 3 * 16 * 4;  // (m, k2, w2) of 9 components x 16 pixels
+constexpr int kCompBytes = 9 * 16 * 16;  // (m, k2, w2, 0) of 9 components x 16 pixels
 
 // blocks in flight per wavefront, beyond the blocks of the current pair
 template <int kEng> constexpr int kTilePF = kEng == kEngValu ? 3 : 6;
@@ -305,7 +305,7 @@ struct BlockLds {
   unsigned *tmask, *pmask, *nmask;
   int* trange;  // [0..8] first and [9..17] last tile of each component's live range
   float* halo;
-  float* comp;  // (m, k2, w2) of each component, comp[(3 k + f) * 16 + i16]
+  float* comp;  // (m, k2, w2, 0) of component k of pixel i16 at comp[4 (16 k + i16)]
   _Float16* ring;
 };
 
@@ -448,9 +448,7 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
   if (g == 0) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      B.comp[(3 * k + 0) * 16 + i16] = C.m[k];
-      B.comp[(3 * k + 1) * 16 + i16] = C.k2[k];
-      B.comp[(3 * k + 2) * 16 + i16] = C.w2[k];
+      *reinterpret_cast<float4*>(B.comp + 4 * (16 * k + i16)) = make_float4(C.m[k], C.k2[k], C.w2[k], 0.f);
     }
   }
   wave_sync();
@@ -668,44 +666,44 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
           const int TAv = lane < 9 ? trange[lane] : 1, TBv = lane < 9 ? trange[9 + lane] : 0;
           tmk = (unsigned)__ballot(TAv <= dt && dt <= TBv) & 0x1ffu;
         }
-        // log2 f by an online log-sum-exp over the live components
-        float mx[4], sm[4];
-        unsigned bits = tmk;
-        const bool single = __builtin_popcount(tmk) == 1;
-        {
-          const int k = bits ? __builtin_ctz(bits) : 0;
-          bits &= bits - 1u;
-          const float mk = comp[(3 * k) * 16 + i16], kk = comp[(3 * k + 1) * 16 + i16];
-          const float wk = tmk ? comp[(3 * k + 2) * 16 + i16] : -INFINITY;
+        // log2 f by a log-sum-exp over the live components: their maximum,
+        // then the sum of exp2 of each below it (one exp2 per component)
+        const float4* cp = reinterpret_cast<const float4*>(comp) + i16;
+        float lp[4];
+        if (__builtin_popcount(tmk) <= 1) {
+          const float4 c = cp[16 * (tmk ? __builtin_ctz(tmk) : 0)];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float e = (float)(dbase + q) - mk;
-            mx[q] = fmaf(-e * e, kk, wk);
-            sm[q] = 1.f;
+            const float e = (float)(dbase + q) - c.x;
+            lp[q] = tmk ? fmaf(-e * e, c.y, c.z) : -INFINITY;
           }
-        }
-        while (bits) {
-          const int k = __builtin_ctz(bits);
-          bits &= bits - 1u;
-          const float mk = comp[(3 * k) * 16 + i16], kk = comp[(3 * k + 1) * 16 + i16];
-          const float wk = comp[(3 * k + 2) * 16 + i16];
+        } else {
+          float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY}, sm[4] = {0.f, 0.f, 0.f, 0.f};
+          for (unsigned bits = tmk; bits; bits &= bits - 1u) {
+            const float4 c = cp[16 * __builtin_ctz(bits)];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float e = (float)(dbase + q) - mk;
-            const float qv = fmaf(-e * e, kk, wk);
-            const float nm = fmaxf(mx[q], qv);
-            const float sa = nm == -INFINITY ? 0.f : fast_exp2(mx[q] - nm);
-            const float sb = nm == -INFINITY ? 0.f : fast_exp2(qv - nm);
-            sm[q] = fmaf(sm[q], sa, sb);
-            mx[q] = nm;
+            for (int q = 0; q < 4; ++q) {
+              const float e = (float)(dbase + q) - c.x;
+              mx[q] = fmaxf(mx[q], fmaf(-e * e, c.y, c.z));
+            }
           }
+          // a pixel with none of these components alive keeps -inf
+#pragma unroll
+          for (int q = 0; q < 4; ++q) mx[q] = mx[q] == -INFINITY ? 0.f : mx[q];
+          for (unsigned bits = tmk; bits; bits &= bits - 1u) {
+            const float4 c = cp[16 * __builtin_ctz(bits)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float e = (float)(dbase + q) - c.x;
+              sm[q] += fast_exp2(fmaf(-e * e, c.y, c.z) - mx[q]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) lp[q] = mx[q] + fast_log2(sm[q]);
         }
         float Lq[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float lp = (single || mx[q] == -INFINITY) ? mx[q] : mx[q] + fast_log2(sm[q]);
-          Lq[q] = (L.valid && dbase + q <= dhi) ? fmaf(acc[q], cs2, lp) : -INFINITY;
-        }
+        for (int q = 0; q < 4; ++q) Lq[q] = (L.valid && dbase + q <= dhi) ? fmaf(acc[q], cs2, lp[q]) : -INFINITY;
         float mt = Lq[0];
         int qt = 0;
 #pragma unroll
@@ -810,11 +808,18 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
             const bool all = __any(pm >= thr);
             if (all || ((pbits >> (m - pbase)) & 1u)) {
               if constexpr (kSplit) {
+                // the low-part operands are all read before the first product
+                half8 Alo[2][NBP];
+#pragma unroll
+                for (int b = 0; b < NBP; ++b) {
+                  Alo[0][b] = a_op(sA, NBP, 1, 0, b, lane);
+                  Alo[1][b] = a_op(sA, NBP, 1, 1, b, lane);
+                }
                 floatx4 l0 = {0.f, 0.f, 0.f, 0.f}, l1 = l0;
 #pragma unroll
                 for (int b = 0; b < NBP; ++b) {
-                  l0 = mfma16(a_op(sA, NBP, 1, 0, b, lane), blk[b], l0);
-                  l1 = mfma16(a_op(sA, NBP, 1, 1, b, lane), blk[b], l1);
+                  l0 = mfma16(Alo[0][b], blk[b], l0);
+                  l1 = mfma16(Alo[1][b], blk[b], l1);
                 }
                 a0 = a0 + l0;
                 a1 = a1 + l1;
