@@ -21,9 +21,12 @@
 // is gathered in fp32. With L = ell + log f the log2 pseudo-posterior,
 // Llb = ell(d_ref) + log f(d_ref) <= L*, and with a margin Lambda = ell(d_ref)
 // + kLambdaGap, every depth d where ell(d) <= Lambda and every prior component
-// is below X = log f(d_ref) - 160 - log2(9) - kLambdaGap satisfies
-// L(d) < Llb - 160 <= L* - 160: exp2(L - L*) is below the smallest fp32
-// denormal, so d contributes exactly zero weight and cannot be the argmax.
+// is below X = log f(d_ref) - 64 - log2(9) - kLambdaGap satisfies
+// L(d) < Llb - 64 <= L* - 64: d cannot be the argmax, and its weight
+// exp2(L - L*) is below 2^-64 of the largest one. At most D <= 2^12 depths
+// are skipped, so their total weight is below 2^-52 of the maximum (which
+// adds 1 to the weight sum): 28 bits under the fp32 resolution of the sums,
+// and their share of the second moment below 2^-52 D^2 <= 2^-28 bin^2.
 // Per component, q_k >= X holds on an interval; the 16-bin tiles meeting any
 // pixel's interval are candidates. The stream computes the exact cost of
 // every pair of tiles; a pair is evaluated when it holds a candidate tile or
@@ -44,7 +47,7 @@ typedef _Float16 half2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRingT = 256;            // LDS ring per pixel (fp16 bins), VALU engine
-constexpr float kCullMargin2 = 160.f;  // log2 units: exp2(-150) rounds to zero in fp32
+constexpr float kCullMargin2 = 64.f;  // log2 units: skipped weights below 2^-64 of the largest
 constexpr float kLog2Nine = 3.16992500144231236f;
 constexpr float kLiveGap = 40.f;        // log2 units
 constexpr unsigned kOob = 0x80000000u;  // buffer offset past every record: loads return zeros
@@ -390,7 +393,7 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
   for (int k = 0; k < 9; ++k) wave_live |= (__any(L.valid && (C.live >> k & 1u)) ? 1u : 0u) << k;
   const float lref2 = lref * M.scale2;
   Lam = lref2 + kLambdaGap;
-  // X = Llb - 160 - Lambda - log2(9), with Llb = lref2 + log f(d_ref)
+  // X = Llb - 64 - Lambda - log2(9), with Llb = lref2 + log f(d_ref)
   const float theta = L.valid
       ? log_prior2(C, (float)dref, wave_live) - kCullMargin2 - kLambdaGap - kLog2Nine
       : INFINITY;
