@@ -40,9 +40,9 @@ def algorithmic_bytes_per_pixel_frame(T: int) -> int:
     return 2 * T + 16 + 16 + 24
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_tile_fp16x2_hist256x256x4096.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_tile_step_fp16x2_hist256x256x4096.json")
 KERNEL_SRCS = ["paper_2004_09211_amd/csrc/k_tile.hip", "paper_2004_09211_amd/csrc/r3d_device.hpp",
-               "paper_2004_09211_amd/csrc/r3d_tile.hpp"]
+               "paper_2004_09211_amd/csrc/r3d_tile.hpp", "paper_2004_09211_amd/build.py"]
 
 
 def measured_traffic(precision: str, frames: int):
