@@ -907,23 +907,30 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   }
 }
 
-// LDS of the workgroup: irf and irf^beta (fp32), the A operands, then each
-// wavefront's masks, halo and (VALU engine) histogram ring.
+// LDS of the workgroup: irf and irf^beta (fp32), irf^beta's fp16 hi and lo
+// parts, the A operands, then each wavefront's region and the shared chunk
+// region. The fp16 parts are staged in LDS first (one coalesced load per
+// tap), so that the A operands are built from LDS rather than from scattered
+// 2-byte global loads.
 template <int kEng, int NBP>
 __device__ __forceinline__ void tile_prologue(const DevModel& M, const TileGeom& G,
                                               unsigned char* smem) {
   float* sh_irf = reinterpret_cast<float*>(smem);
   float* sh_h = sh_irf + M.W;
+  _Float16* sh16 = reinterpret_cast<_Float16*>(sh_h + M.W);  // [0, W) hi, [W, 2W) lo
   for (int j = threadIdx.x; j < M.W; j += blockDim.x) {
     sh_irf[j] = M.irf[j];
     sh_h[j] = M.h[j];
+    sh16[j] = M.h16hi[j];
+    sh16[M.W + j] = M.h16lo[j];
   }
   if constexpr (kEng != kEngValu) {
+    __syncthreads();
     half8* sA = reinterpret_cast<half8*>(smem + G.lds_a);
     for (int e = threadIdx.x; e < 2 * 2 * NBP * 64; e += blockDim.x) {
       const int ln = e & 63, b = (e >> 6) % NBP, tau = (e / (64 * NBP)) & 1, part = e / (128 * NBP);
       const int g = ln >> 4, i16 = ln & 15;
-      const _Float16* src = part ? M.h16lo : M.h16hi;
+      const _Float16* src = sh16 + (part ? M.W : 0);
       const bool scale = part == 0 && kEng == kEngMfma16x2;
       half8 v;
 #pragma unroll
@@ -1020,7 +1027,7 @@ bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
   // workgroup: irf and irf^beta (fp32) and the A operands; then one region
   // per wavefront: masks, component tile ranges, halo, components and (VALU
   // engine) the ring
-  G.lds_a = ((8 * M.W + 15) / 16) * 16;
+  G.lds_a = ((12 * M.W + 15) / 16) * 16;  // irf, irf^beta (fp32), fp16 hi and lo
   G.lds_fixed = G.lds_a + (engine == kEngValu ? 0 : 2 * 2 * G.nbp * 64 * 16);
   G.off_trange = ((4 * (G.mask_words + G.pair_words + G.need_words) + 15) / 16) * 16;
   G.off_halo = G.off_trange + 80;
