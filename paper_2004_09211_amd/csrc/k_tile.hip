@@ -521,27 +521,32 @@ __device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io,
 }
 
 // ============================ shared blocks ============================
-// A block whose pairs are shared by the four wavefronts of its workgroup:
-// wavefront 0 prepares it and publishes its margins; its pairs are then
-// taken in chunks from a counter by wavefront 0 and, once their own blocks
-// are done, by the other three. Each chunk's moments go to a slot of their
-// own and are merged in chunk order, so the result does not depend on which
-// wavefront took which chunk.
+// A dense block (candidate tiles on many of its pairs: a frame border, a
+// flat or wide prior) can be shared by the four wavefronts of its workgroup.
+// The dense block of the lowest-numbered wavefront owns the workgroup's share
+// region (a choice made by the data alone): its wavefront publishes the
+// margins and streams the block in chunks of pairs taken from the front; the
+// other wavefronts, once their own blocks are done, take chunks from the
+// back. Each chunk's moments go to a slot of their own and are merged in
+// chunk order, so the result does not depend on which wavefront took which
+// chunk.
 struct ShareLds {
-  unsigned* ctl;  // [0] published, [1] block shared, [2] next chunk, [3] live components
+  unsigned* ctl;  // [0] wavefronts decided, [1] owner wavefront + 1 (0: none),
+                  // [2] chunk claims (next front | end of the back << 16), [3] live components,
+                  // [4 + w] wavefront w's decision (0: pending, 1: not dense, 2: dense)
   float* lam;     // [16] cost margin of each pixel
   unsigned* K;    // [16] photon count of each pixel (integer sums: exact in any order)
   float* slot;    // [kMaxChunks][5][16] moments of each chunk
 };
 
-constexpr int kShareBytes = (36 + kMaxChunks * 5 * 16) * 4;
+constexpr int kShareBytes = (40 + kMaxChunks * 5 * 16) * 4;
 
 __device__ __forceinline__ ShareLds share_lds(const TileGeom& G, unsigned char* smem) {
   ShareLds S;
   S.ctl = reinterpret_cast<unsigned*>(smem + G.off_share);
-  S.lam = reinterpret_cast<float*>(S.ctl + 4);
-  S.K = S.ctl + 20;
-  S.slot = reinterpret_cast<float*>(S.ctl + 36);
+  S.lam = reinterpret_cast<float*>(S.ctl + 8);
+  S.K = S.ctl + 24;
+  S.slot = reinterpret_cast<float*>(S.ctl + 40);
   return S;
 }
 
@@ -558,13 +563,13 @@ __device__ __forceinline__ Moments get_moments(const float* s, int i16) {
 }
 
 // ============================ one wavefront ============================
-// The wavefront's tasks: its own block (whole, or the first chunk when it is
-// wavefront 0 and its block is shared), then chunks of the shared block.
-// Each task streams its pairs through the register ring (the blocks of the
-// current pair plus kTilePF prefetched ones): photon count and count
-// validation on every block, the exact cost of both tiles of every pair, the
-// posterior on the pairs that need it. After the workgroup barrier each
-// wavefront finishes its own block (a6, a7).
+// The wavefront's tasks: its own block (whole, or in chunks when it owns the
+// shared block), then chunks of the shared block. Each task streams its
+// pairs through the register ring (the blocks of the current pair plus
+// kTilePF prefetched ones): photon count and count validation on every
+// block, the exact cost of both tiles of every pair, the posterior on the
+// pairs that need it. After the workgroup barrier each wavefront finishes its
+// own block (a6, a7).
 template <int kEng, int NBP>
 __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, const StepIO& io,
                                           int idx, int wave, const half8* sA, const float* sh_irf,
@@ -575,6 +580,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   const int i16 = lane & 15, g = lane >> 4;
   const int dhi = M.d_lo + M.D - 1;
   const float cs2 = M.scale2 * (kSplit ? (1.0f / 2048.0f) : 1.0f);  // raw cost -> log2 units
+  const int ngrp = (G.nblk + 3) >> 2;  // workgroups; wavefront w takes block w * ngrp + j
   const bool active = idx < G.nblk;
   unsigned char* wown = smem + G.lds_fixed + wave * G.lds_per_wave;
   _Float16* ring_lds = block_lds(G, wown).ring;
@@ -606,35 +612,70 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
       for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + x);
     });
   const bool own_faulty = L.faulty;
-  bool shared = false;
-  if (wave == 0) {
-    // a block with candidate tiles on most pairs (a frame border, a flat
-    // prior) is shared
+  // a dense block (candidate tiles on at least an eighth of its pairs) is
+  // shared when no lower-numbered wavefront has one: a dense wavefront
+  // waits (bounded) for the decisions of the lower ones, which finish their
+  // preparation at about the same time. The owner publishes the margins,
+  // then every wavefront with a block counts itself decided.
+  bool owner = false;
+  if (active) {
     int ncand = 0;
     for (int w = 0; w < G.pair_words; ++w)
       ncand += __builtin_popcount(__builtin_amdgcn_readfirstlane(B.pmask[w]));
-    shared = G.nchunks >= 2 && 4 * ncand >= G.npairs;
-    if (g == 0) {
-      S.lam[i16] = Lam;
-      S.K[i16] = 0u;
+    const bool dense = G.nchunks >= 2 && 8 * ncand >= G.npairs;
+    if (lane == 0)
+      __hip_atomic_store(&S.ctl[4 + wave], dense ? 2u : 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (dense) {
+      owner = true;
+      for (int v = 0; v < wave && owner; ++v) {
+        unsigned dv = 0u;
+        for (int n = 0; n < (1 << 20) && dv == 0u; ++n) {
+          dv = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(&S.ctl[4 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+          if (dv == 0u) __builtin_amdgcn_s_sleep(4);
+        }
+        owner = dv == 1u;  // a lower dense block (or no answer) keeps this one unshared
+      }
     }
-    if (lane == 0) {
-      S.ctl[1] = shared ? 1u : 0u;
-      S.ctl[2] = 1u;
-      S.ctl[3] = wave_live;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (lane == 0) __hip_atomic_store(&S.ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (shared) {
+    if (owner) {
+      if (g == 0) {
+        S.lam[i16] = Lam;
+        S.K[i16] = 0u;
+      }
+      if (lane == 0) {
+        S.ctl[1] = (unsigned)wave + 1u;
+        S.ctl[2] = 1u | ((unsigned)G.nchunks << 16);  // chunk 0 is the owner's
+        S.ctl[3] = wave_live;
+      }
+      // the owner's ring runs on from one chunk into the next (kb_end stays
+      // at the end of the block)
       c = 0;
       me = G.chunk < G.npairs ? G.chunk : G.npairs;
-      kb_end = G.kbA0 + me + NBP - 2;
     }
+    if (lane == 0) __hip_atomic_fetch_add(&S.ctl[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+  int nactive = 0;
+  for (int w = 0; w < 4; ++w) nactive += (w * ngrp + (int)blockIdx.x < G.nblk) ? 1 : 0;
 
-  half8 ones;
-#pragma unroll
-  for (int s = 0; s < 8; ++s) ones[s] = (_Float16)1.f;
+  // take a chunk of the shared block: the owner from the front, the others
+  // from the back (-1 once the two ends meet); each chunk is taken once
+  auto claim = [&](bool front) __attribute__((always_inline)) -> int {
+    int got = -1;
+    if (lane == 0) {
+      unsigned old = __hip_atomic_load(&S.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      for (;;) {
+        const unsigned f = old & 0xffffu, b = old >> 16;
+        if (f >= b) break;
+        const unsigned seen = atomicCAS(&S.ctl[2], old, front ? old + 1u : old - 0x10000u);
+        if (seen == old) {
+          got = front ? (int)f : (int)b - 1;
+          break;
+        }
+        old = seen;
+      }
+    }
+    return __builtin_amdgcn_readfirstlane(got);
+  };
   auto is_cand = [&](const unsigned* mk, int i) __attribute__((always_inline)) -> bool {
     return (__builtin_amdgcn_readfirstlane(mk[i >> 5]) >> (i & 31)) & 1u;
   };
@@ -752,6 +793,37 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
 #pragma unroll
         for (int s = 0; s < 4; ++s) Kv = __builtin_amdgcn_fdot2(half2{v[2 * s], v[2 * s + 1]}, one2, Kv, false);
       };
+      // the task's moments and photon count, lane-merged, to the own region
+      // (cc < 0) or to chunk cc's slot
+      auto flush = [&](int cc) __attribute__((always_inline)) {
+        const float K = group_sum<16, 32>(Kv);
+        Moments mm = mo;
+        lane_merge(mm);
+        if (g == 0) {
+          if (cc < 0) {
+            float* own = block_lds(G, wown).halo;  // the halo is dead once the prior is built
+            put_moments(own, mm, i16);
+            own[80 + i16] = K;
+          } else {
+            put_moments(S.slot + cc * 80, mm, i16);
+            atomicAdd(&S.K[i16], (unsigned)K);
+          }
+        }
+        mo = Moments{-INFINITY, 0.f, 0.f, 0.f, 0.f};
+        Kv = 0.f;
+      };
+      if (first) {
+        // blocks of [0, T) that no depth window reaches still hold photons
+        for (int kb = 0; kb < G.nkb; ++kb) {
+          if (kb >= G.kbA0 && kb <= G.kb_last) continue;
+          account(load_block(M, L, g, kb));
+        }
+      }
+      // the owner's own task runs through its chunks without reloading the
+      // ring: at each chunk end (chunks are whole ring rounds) it flushes and
+      // takes the next chunk from the front
+      const bool run_on = owner && first;
+      bool flushed = false;
       for (int m0 = mb; m0 < me; m0 += RING) {
         // candidate-pair bits of pairs m0 .. m0 + RING - 1 (< 41 bits past
         // pbase)
@@ -832,57 +904,45 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
             }
           }
         }
-      }
-      if (first) {
-        // blocks of [0, T) that no depth window reaches still hold photons
-        for (int kb = 0; kb < G.nkb; ++kb) {
-          if (kb >= G.kbA0 && kb <= G.kb_last) continue;
-          account(load_block(M, L, g, kb));
+        if (run_on && m0 + RING == me && me < G.npairs) {
+          flush(c);
+          const int nc = claim(true);
+          if (nc < 0) {
+            flushed = true;
+            break;
+          }
+          c = nc;  // == c + 1: the chunks taken from the front are consecutive
+          me = me + G.chunk < G.npairs ? me + G.chunk : G.npairs;
         }
       }
       // > 2048 or negative
       const unsigned bad = (vmax[0] > 0x6800u || vmax[1] > 0x6800u) ? kErrOverflow : 0u;
       if (bad) atomicOr(M.err, bad);
-      const float K = group_sum<16, 32>(Kv);
-      lane_merge(mo);
-      if (g == 0) {
-        if (c < 0) {
-          float* own = block_lds(G, wown).halo;  // the halo is dead once the prior is built
-          put_moments(own, mo, i16);
-          own[80 + i16] = K;
-        } else {
-          put_moments(S.slot + c * 80, mo, i16);
-          atomicAdd(&S.K[i16], (unsigned)K);
-        }
-      }
+      if (!flushed) flush(c);
       first = false;
     }
     if (!helping) {
       helping = true;
-      bool join = shared;
-      if (wave != 0) {
-        // wait (bounded) for wavefront 0 to publish; a wavefront that gives
-        // up leaves the chunks to the others, which take all of them
-        bool pub = false;
-        for (int n = 0; n < (1 << 20) && !pub; ++n) {
-          pub = __builtin_amdgcn_readfirstlane(
-                    __hip_atomic_load(&S.ctl[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0u;
-          if (!pub) __builtin_amdgcn_s_sleep(4);
-        }
-        join = pub && __builtin_amdgcn_readfirstlane(S.ctl[1]) != 0u;
-        if (join) {
-          L = lane_pixel(M, G, io.hist, io.faulty, blockIdx.x, i16, g);
-          B = block_lds(G, smem + G.lds_fixed);
-          thr = margin_bits(S.lam[i16]);
-          wave_live = __builtin_amdgcn_readfirstlane(S.ctl[3]);
-        }
+      if (owner) break;  // its chunks were taken in its own task
+      // wait (bounded) until every wavefront with a block has decided; a
+      // wavefront that gives up leaves the chunks to the others, which take
+      // all of them
+      bool decided = false;
+      for (int n = 0; n < (1 << 20) && !decided; ++n) {
+        decided = (int)__builtin_amdgcn_readfirstlane(
+                      __hip_atomic_load(&S.ctl[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) >= nactive;
+        if (!decided) __builtin_amdgcn_s_sleep(4);
       }
-      if (!join) break;
+      const unsigned ow = decided ? __builtin_amdgcn_readfirstlane(S.ctl[1]) : 0u;
+      if (ow == 0u) break;
+      const int oi = (int)ow - 1;
+      L = lane_pixel(M, G, io.hist, io.faulty, oi * ngrp + (int)blockIdx.x, i16, g);
+      B = block_lds(G, smem + G.lds_fixed + oi * G.lds_per_wave);
+      thr = margin_bits(S.lam[i16]);
+      wave_live = __builtin_amdgcn_readfirstlane(S.ctl[3]);
     }
-    int cv = 0;
-    if (lane == 0) cv = (int)atomicAdd(&S.ctl[2], 1u);
-    c = __builtin_amdgcn_readfirstlane(cv);
-    if (c >= G.nchunks) break;
+    c = claim(false);
+    if (c < 0) break;
     mb = c * G.chunk;
     me = mb + G.chunk < G.npairs ? mb + G.chunk : G.npairs;
     kb_end = G.kbA0 + me + NBP - 2;
@@ -892,7 +952,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   if (active) {
     Moments mo;
     float K;
-    if (wave == 0 && shared) {
+    if (owner) {
       mo = Moments{-INFINITY, 0.f, 0.f, 0.f, 0.f};
       for (int k = 0; k < G.nchunks; ++k) merge_moments(mo, get_moments(S.slot + k * 80, i16));
       K = (float)S.K[i16];
@@ -952,7 +1012,10 @@ template <int kEng, int NBP>
 __global__ void __launch_bounds__(256, NBP <= 3 ? 4 : 2) k_tile_step(DevModel M, TileGeom G,
                                                                       StepIO io) {
   extern __shared__ __align__(16) unsigned char smem[];
-  if (threadIdx.x == 0) reinterpret_cast<unsigned*>(smem + G.off_share)[0] = 0u;
+  if (threadIdx.x < 8) {
+    // no wavefront decided yet, no shared block, no decisions
+    if (threadIdx.x < 2 || threadIdx.x >= 4) reinterpret_cast<unsigned*>(smem + G.off_share)[threadIdx.x] = 0u;
+  }
   tile_prologue<kEng, NBP>(M, G, smem);
   // the wavefront index is uniform: say so, so that everything derived from
   // it (the block, its buffer descriptor, the task switches) stays scalar
@@ -1036,11 +1099,13 @@ bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
   G.lds_per_wave = G.off_ring + (engine == kEngValu ? 16 * kRingT * 2 : 0);
   G.off_share = G.lds_fixed + 4 * G.lds_per_wave;
   G.lds_total = G.off_share + kShareBytes;
-  // chunks of at least 8 pairs: the ring's first RING - 1 blocks are loaded
-  // before the block's chunking is known and must lie in the band of its
-  // first chunk (RING - NBP <= 6)
-  G.chunk = (G.npairs + kMaxChunks - 1) / kMaxChunks;
-  if (G.chunk < 8) G.chunk = 8;
+  // chunks of a whole number of ring rounds (RING pairs), at most
+  // kMaxChunks of them: the owner of a shared block streams on from one
+  // chunk into the next at the end of a round, and the ring's first
+  // RING - 1 blocks, loaded before the block's chunking is known, lie in
+  // the band of its first chunk
+  const int ring = G.nbp + (engine == kEngValu ? kTilePF<kEngValu> : kTilePF<kEngMfma16x2>);
+  G.chunk = ring * ((G.npairs + kMaxChunks * ring - 1) / (kMaxChunks * ring));
   G.nchunks = (G.npairs + G.chunk - 1) / G.chunk;
   if (engine == kEngValu && 32 * G.nbp > kRingT) return false;
   return G.lds_total <= 65536;
