@@ -612,8 +612,9 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
       for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + x);
     });
   const bool own_faulty = L.faulty;
-  // a dense block (candidate tiles on at least an eighth of its pairs) is
-  // shared when no lower-numbered wavefront has one: a dense wavefront
+  // a dense block (candidate tiles on at least a 32nd of its pairs: most
+  // blocks but the plainest) is shared when no lower-numbered wavefront has
+  // one, so that the workgroup's wavefronts end together: a dense wavefront
   // waits (bounded) for the decisions of the lower ones, which finish their
   // preparation at about the same time. The owner publishes the margins,
   // then every wavefront with a block counts itself decided.
@@ -622,7 +623,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
     int ncand = 0;
     for (int w = 0; w < G.pair_words; ++w)
       ncand += __builtin_popcount(__builtin_amdgcn_readfirstlane(B.pmask[w]));
-    const bool dense = G.nchunks >= 2 && 8 * ncand >= G.npairs;
+    const bool dense = G.nchunks >= 2 && 32 * ncand >= G.npairs;
     if (lane == 0)
       __hip_atomic_store(&S.ctl[4 + wave], dense ? 2u : 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (dense) {
