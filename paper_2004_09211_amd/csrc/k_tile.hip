@@ -253,7 +253,7 @@ __device__ __forceinline__ void halo_components(const DevModel& M, const float* 
     const float m = det ? halo[idx] : M.m_flat;
     const float V = (det ? halo[36 + idx] : M.v_flat) + M.sigma_rw2;
     C.m[k] = m;
-    C.k2[k] = 0.5f * kLog2e / V;
+    C.k2[k] = 0.5f * kLog2e * fast_rcp(V);
     C.w2[k] = M.lognu2[k] - 0.5f * (kLog2TwoPi + fast_log2(V));
   }
   merge_components(C);
