@@ -57,6 +57,9 @@ constexpr int kCompBytes = 9 * 16 * 16;  // (m, k2, w2, 0) of 9 components x 16 
 
 // blocks in flight per wavefront, beyond the blocks of the current pair
 template <int kEng> constexpr int kTilePF = kEng == kEngValu ? 3 : 6;
+// wavefronts per workgroup of the step (the vector-FMA engine keeps an LDS
+// ring per wavefront, so it stays at 4)
+template <int kEng> constexpr int kWavesOf = kEng == kEngValu ? 4 : kTileWaves;
 constexpr float kLambdaGap = 32.f;  // log2 units: cost margin above ell(d_ref)
 // absolute slack of the fp16-hi cost in the split engine's raw units (hi
 // scaled by 2^11): 256 taps x count 2048 x 2^-25 x 2^11
@@ -522,7 +525,7 @@ __device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io,
 
 // ============================ shared blocks ============================
 // A dense block (candidate tiles on many of its pairs: a frame border, a
-// flat or wide prior) can be shared by the four wavefronts of its workgroup.
+// flat or wide prior) can be shared by the wavefronts of its workgroup.
 // The dense block of the lowest-numbered wavefront owns the workgroup's share
 // region (a choice made by the data alone): its wavefront publishes the
 // margins and streams the block in chunks of pairs taken from the front; the
@@ -539,14 +542,16 @@ struct ShareLds {
   float* slot;    // [kMaxChunks][5][16] moments of each chunk
 };
 
-constexpr int kShareBytes = (40 + kMaxChunks * 5 * 16) * 4;
+// control words: 4, then one decision per wavefront, padded to 8 words
+constexpr int kCtlWords = (4 + kTileWaves + 7) / 8 * 8;
+constexpr int kShareBytes = (kCtlWords + 32 + kMaxChunks * 5 * 16) * 4;
 
 __device__ __forceinline__ ShareLds share_lds(const TileGeom& G, unsigned char* smem) {
   ShareLds S;
   S.ctl = reinterpret_cast<unsigned*>(smem + G.off_share);
-  S.lam = reinterpret_cast<float*>(S.ctl + 8);
-  S.K = S.ctl + 24;
-  S.slot = reinterpret_cast<float*>(S.ctl + 40);
+  S.lam = reinterpret_cast<float*>(S.ctl + kCtlWords);
+  S.K = S.ctl + kCtlWords + 16;
+  S.slot = reinterpret_cast<float*>(S.ctl + kCtlWords + 32);
   return S;
 }
 
@@ -580,7 +585,8 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   const int i16 = lane & 15, g = lane >> 4;
   const int dhi = M.d_lo + M.D - 1;
   const float cs2 = M.scale2 * (kSplit ? (1.0f / 2048.0f) : 1.0f);  // raw cost -> log2 units
-  const int ngrp = (G.nblk + 3) >> 2;  // workgroups; wavefront w takes block w * ngrp + j
+  constexpr int NW = kWavesOf<kEng>;
+  const int ngrp = (G.nblk + NW - 1) / NW;  // workgroups; wavefront w takes block w * ngrp + j
   const bool active = idx < G.nblk;
   unsigned char* wown = smem + G.lds_fixed + wave * G.lds_per_wave;
   _Float16* ring_lds = block_lds(G, wown).ring;
@@ -656,7 +662,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
     if (lane == 0) __hip_atomic_fetch_add(&S.ctl[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   int nactive = 0;
-  for (int w = 0; w < 4; ++w) nactive += (w * ngrp + (int)blockIdx.x < G.nblk) ? 1 : 0;
+  for (int w = 0; w < NW; ++w) nactive += (w * ngrp + (int)blockIdx.x < G.nblk) ? 1 : 0;
 
   // take a chunk of the shared block: the owner from the front, the others
   // from the back (-1 once the two ends meet); each chunk is taken once
@@ -1010,10 +1016,10 @@ __device__ __forceinline__ void tile_prologue(const DevModel& M, const TileGeom&
 // the border blocks (first in block order) fall on wavefront 0 of distinct
 // workgroups and each can be shared by its workgroup.
 template <int kEng, int NBP>
-__global__ void __launch_bounds__(256, NBP <= 3 ? 4 : 2) k_tile_step(DevModel M, TileGeom G,
+__global__ void __launch_bounds__(64 * kWavesOf<kEng>, NBP <= 3 ? 4 : 2) k_tile_step(DevModel M, TileGeom G,
                                                                       StepIO io) {
   extern __shared__ __align__(16) unsigned char smem[];
-  if (threadIdx.x < 8) {
+  if (threadIdx.x < 4 + kWavesOf<kEng>) {
     // no wavefront decided yet, no shared block, no decisions
     if (threadIdx.x < 2 || threadIdx.x >= 4) reinterpret_cast<unsigned*>(smem + G.off_share)[threadIdx.x] = 0u;
   }
@@ -1021,7 +1027,7 @@ __global__ void __launch_bounds__(256, NBP <= 3 ? 4 : 2) k_tile_step(DevModel M,
   // the wavefront index is uniform: say so, so that everything derived from
   // it (the block, its buffer descriptor, the task switches) stays scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int idx = wave * ((G.nblk + 3) >> 2) + (int)blockIdx.x;  // the grid has (nblk + 3) / 4 workgroups
+  const int idx = wave * ((G.nblk + kWavesOf<kEng> - 1) / kWavesOf<kEng>) + (int)blockIdx.x;
   const float* sh_irf = reinterpret_cast<const float*>(smem);
   const float* sh_h = sh_irf + M.W;
   const half8* sA = reinterpret_cast<const half8*>(smem + G.lds_a);
@@ -1098,7 +1104,8 @@ bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
   G.off_comp = G.off_halo + kHaloBytes;
   G.off_ring = G.off_comp + kCompBytes;
   G.lds_per_wave = G.off_ring + (engine == kEngValu ? 16 * kRingT * 2 : 0);
-  G.off_share = G.lds_fixed + 4 * G.lds_per_wave;
+  G.waves = engine == kEngValu ? kWavesOf<kEngValu> : kWavesOf<kEngMfma16x2>;
+  G.off_share = G.lds_fixed + G.waves * G.lds_per_wave;
   G.lds_total = G.off_share + kShareBytes;
   // chunks of a whole number of ring rounds (RING pairs), at most
   // kMaxChunks of them: the owner of a shared block streams on from one
@@ -1117,7 +1124,7 @@ template <int kEng>
 static hipError_t launch_step_eng(const DevModel& M, const TileGeom& G, const StepIO& io,
                                   hipStream_t s) {
   const size_t lds = G.lds_total;
-  const dim3 grid((G.nblk + 3) / 4), block(256);
+  const dim3 grid((G.nblk + G.waves - 1) / G.waves), block(64 * G.waves);
   if (G.nblk < 1) return hipErrorInvalidValue;
   switch (G.nbp) {
     case 2: hipLaunchKernelGGL((k_tile_step<kEng, 2>), grid, block, lds, s, M, G, io); break;

@@ -9,6 +9,11 @@ namespace r3d {
 enum { kEngValu = 0, kEngMfma16 = 1, kEngMfma16x2 = 2 };
 constexpr int kTileMaxNBP = 5;  // 32-bin blocks spanned by a 32-bin pair of depth tiles
 constexpr int kMaxChunks = 16;  // chunks of pairs of a block shared by a workgroup's wavefronts
+#ifndef R3D_TILE_WAVES
+#define R3D_TILE_WAVES 4
+#endif
+constexpr int kTileWaves = R3D_TILE_WAVES;  // wavefronts (4x4 pixel blocks) per workgroup of the
+                                            // matrix-core step (4 for the vector-FMA engine)
 
 struct TileGeom {
   int o;           // (d_lo - c) mod 32
@@ -30,6 +35,7 @@ struct TileGeom {
   int lds_total;   // bytes of LDS of one workgroup
   int chunk;       // pairs per chunk of a shared block
   int nchunks;     // ceil(npairs / chunk) <= kMaxChunks
+  int waves;       // wavefronts per workgroup of the step
 };
 
 bool tile_geometry(const DevModel& M, int engine, TileGeom& G);
