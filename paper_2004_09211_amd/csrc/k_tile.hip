@@ -383,20 +383,13 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
 
   Comps C;
   halo_components(M, B.halo, i16, C);
-  float lref = 0.f;
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int j = g + 4 * u;
-    if (j < M.W) lref = fmaf(sh_h[j], zr[u], lref);
-  }
-  lref = group_sum<16, 32>(lref);
 
   wave_live = 0u;
 #pragma unroll
   for (int k = 0; k < 9; ++k) wave_live |= (__any(L.valid && (C.live >> k & 1u)) ? 1u : 0u) << k;
-  const float lref2 = lref * M.scale2;
-  Lam = lref2 + kLambdaGap;
-  // X = Llb - 64 - Lambda - log2(9), with Llb = lref2 + log f(d_ref)
+  // X = Llb - 64 - Lambda - log2(9), with Llb = ell(d_ref) + log f(d_ref) and
+  // Lambda = ell(d_ref) + kLambdaGap: the reference cost cancels, so the
+  // candidate tiles do not wait for its gather
   const float theta = L.valid
       ? log_prior2(C, (float)dref, wave_live) - kCullMargin2 - kLambdaGap - kLog2Nine
       : INFINITY;
@@ -450,6 +443,15 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
       set_bits(B.pmask, ta >> 1, tb >> 1);
     }
   }
+  // the reference cost, whose gather has been in flight meanwhile
+  float lref = 0.f;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = g + 4 * u;
+    if (j < M.W) lref = fmaf(sh_h[j], zr[u], lref);
+  }
+  lref = group_sum<16, 32>(lref);
+  Lam = lref * M.scale2 + kLambdaGap;
   // the pixels' components, component-major
   if (g == 0) {
 #pragma unroll
