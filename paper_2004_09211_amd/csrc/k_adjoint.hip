@@ -284,15 +284,29 @@ __global__ void k_adjoint_gather(int rows, int cols, const float* __restrict__ c
   av[q] = sv;
 }
 
-__global__ void k_theta_reduce(DevModel M, const float* __restrict__ part, int blocks,
-                               double* __restrict__ grad) {
+// One workgroup per parameter: each thread sums a fixed stride of the block
+// partials in fp64, then a fixed-order tree over the threads (the same
+// order every run, so the gradient stays bit-reproducible).
+constexpr int kReduceThreads = 256;
+
+__global__ void __launch_bounds__(kReduceThreads) k_theta_reduce(DevModel M, const float* __restrict__ part,
+                                                                 int blocks, double* __restrict__ grad) {
+  __shared__ double red[kReduceThreads];
   const int npar = kThetaFixed + M.W;
-  const double beta = M.beta;
-  const double s_nat = (beta + 1.0) / beta;
-  for (int i = threadIdx.x; i < npar; i += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += (double)part[(size_t)b * npar + i];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < blocks; b += kReduceThreads) s += (double)part[(size_t)b * npar + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    s = red[0];
     if (i >= kThetaFixed) {
+      const double beta = M.beta;
+      const double s_nat = (beta + 1.0) / beta;
       const double f = M.irf[i - kThetaFixed];
       s = f > 0.0 ? s * s_nat * beta * pow(f, beta - 1.0) : 0.0;
     }
@@ -345,7 +359,8 @@ hipError_t launch_adjoint_gather(const DevModel& M, const float* cm, const float
 
 hipError_t launch_theta_reduce(const DevModel& M, const float* part, int blocks, double* grad,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_theta_reduce, dim3(1), dim3(256), 0, s, M, part, blocks, grad);
+  hipLaunchKernelGGL(k_theta_reduce, dim3(kThetaFixed + M.W), dim3(kReduceThreads), 0, s, M, part,
+                     blocks, grad);
   return hipGetLastError();
 }
 
