@@ -218,7 +218,9 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
   accT[1] += sig_bar;
 }
 
-__global__ void __launch_bounds__(256) k_adjoint(DevModel M, AdjIO io) {
+// 4 wavefronts per SIMD (128 VGPRs, a few spills): the pixel passes are
+// latency-bound, and twice the wavefronts in flight halves the stalls
+__global__ void __launch_bounds__(256, 4) k_adjoint(DevModel M, AdjIO io) {
   extern __shared__ __align__(16) float smem[];
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int W = M.W;

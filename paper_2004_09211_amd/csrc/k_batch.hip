@@ -26,7 +26,8 @@ __global__ void k_batch_reset(unsigned* queue, int* done, int ndone) {
   for (int k = i; k < ndone; k += gridDim.x * blockDim.x) done[k] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_batch(const SeqDesc* __restrict__ seqs, BatchGeom B) {
+// 4 wavefronts per SIMD: the photon-list pixels are latency-bound
+__global__ void __launch_bounds__(256, 4) k_batch(const SeqDesc* __restrict__ seqs, BatchGeom B) {
   extern __shared__ __align__(16) float smem[];
   __shared__ unsigned s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
