@@ -308,7 +308,7 @@ __device__ __forceinline__ void lane_merge(Moments& mo) {
 
 // Per-wavefront LDS region of a resolved block.
 struct BlockLds {
-  unsigned *tmask, *pmask, *nmask;
+  unsigned *tmask, *pmask;  // candidate tiles, candidate pairs (then one zero word)
   int* trange;  // [0..8] first and [9..17] last tile of each component's live range
   float* halo;
   float* comp;  // (m, k2, w2, 0) of component k of pixel i16 at comp[4 (16 k + i16)]
@@ -319,7 +319,6 @@ __device__ __forceinline__ BlockLds block_lds(const TileGeom& G, unsigned char* 
   BlockLds B;
   B.tmask = reinterpret_cast<unsigned*>(wbase);
   B.pmask = B.tmask + G.mask_words;
-  B.nmask = B.pmask + G.pair_words;
   B.trange = reinterpret_cast<int*>(wbase + G.off_trange);
   B.halo = reinterpret_cast<float*>(wbase + G.off_halo);
   B.comp = reinterpret_cast<float*>(wbase + G.off_comp);
@@ -419,7 +418,7 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
   }
 
   // candidate tiles and pairs (LDS bit masks, or-ed by the lanes)
-  const int nwords = G.mask_words + G.pair_words + G.need_words;
+  const int nwords = G.mask_words + G.pair_words + 1;  // the pair bits are read 64 at a time
   for (int w = lane; w < nwords; w += 64) B.tmask[w] = 0u;
   wave_sync();
   auto set_bits = [&](unsigned* mk, int a0, int z0) __attribute__((always_inline)) {
@@ -1089,7 +1088,6 @@ bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
   G.ntiles = (M.D + 15) / 16;
   G.mask_words = (G.ntiles + 31) / 32;
   G.pair_words = (G.npairs + 31) / 32;
-  G.need_words = (G.npairs + G.nbp - 1 + 31) / 32;
   G.nkb = (M.T + 31) / 32;
   G.kb_last = G.kbA0 + G.npairs - 1 + G.nbp - 1;
   G.nbc = (M.cols + 3) / 4;
@@ -1101,7 +1099,7 @@ bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
   // engine) the ring
   G.lds_a = ((12 * M.W + 15) / 16) * 16;  // irf, irf^beta (fp32), fp16 hi and lo
   G.lds_fixed = G.lds_a + (engine == kEngValu ? 0 : 2 * 2 * G.nbp * 64 * 16);
-  G.off_trange = ((4 * (G.mask_words + G.pair_words + G.need_words) + 15) / 16) * 16;
+  G.off_trange = ((4 * (G.mask_words + G.pair_words + 1) + 15) / 16) * 16;
   G.off_halo = G.off_trange + 80;
   G.off_comp = G.off_halo + kHaloBytes;
   G.off_ring = G.off_comp + kCompBytes;

@@ -23,7 +23,6 @@ struct TileGeom {
   int ntiles;      // ceil(D / 16)
   int mask_words;  // ceil(ntiles / 32): candidate tiles
   int pair_words;  // ceil(npairs / 32): candidate pairs
-  int need_words;  // ceil((npairs + nbp - 1) / 32): blocks read by candidate pairs
   int nkb;         // ceil(T / 32)
   int kb_last;     // last block touched by the pairs
   int nbc;         // 4x4 pixel blocks per block-row
