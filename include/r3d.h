@@ -162,8 +162,8 @@ r3d_status r3d_step_hist(r3d_ctx *ctx, const uint16_t *hist,
  * nframes * P elements, frame-major; any pointer may be NULL.
  * R3D_EUNSUPPORTED when T is not a multiple of 8 or the IRF is too long for
  * the tile kernels (r3d_step_hist then still runs R3D_FP32 contexts).
- * Asynchronous; uses the context's bound buffers, so a context runs one
- * step or sequence at a time. */
+ * Asynchronous. The context keeps no per-call buffers for this call: only
+ * its error word is shared with other calls. */
 r3d_status r3d_run_hist(r3d_ctx *ctx, const uint16_t *const *hist, int32_t nframes,
                         const float *pi_in, const uint8_t *faulty, const r3d_state *state,
                         const r3d_out *out, void *stream);

@@ -23,18 +23,22 @@
 // + kLambdaGap, every depth d where ell(d) <= Lambda and every prior component
 // is below X = log f(d_ref) - 64 - log2(9) - kLambdaGap satisfies
 // L(d) < Llb - 64 <= L* - 64: d cannot be the argmax, and its weight
-// exp2(L - L*) is below 2^-64 of the largest one. At most D <= 2^12 depths
-// are skipped, so their total weight is below 2^-52 of the maximum (which
-// adds 1 to the weight sum): 28 bits under the fp32 resolution of the sums,
-// and their share of the second moment below 2^-52 D^2 <= 2^-28 bin^2.
+// exp2(L - L*) is below 2^-64 of the largest one. The skipped depths
+// together weigh below D 2^-64 <= 2^-49 of the maximum (D <= 2^15; the
+// maximum adds 1 to the weight sum), 25 bits under the fp32 resolution of
+// the sums, and their share of the second moment is below 2^-64 D^3 bin^2
+// (2^-28 bin^2 at D = 4096).
 // Per component, q_k >= X holds on an interval; the 16-bin tiles meeting any
-// pixel's interval are candidates. The stream computes the exact cost of
-// every pair of tiles; a pair is evaluated when it holds a candidate tile or
-// when some pixel's cost in it exceeds Lambda (then with every component of
-// the mixture). The argmax and the centred moments are accumulated online
+// pixel's interval are candidates. The stream computes the fp16-hi cost of
+// every pair of tiles; a pair is evaluated (low part added: the exact cost)
+// when it holds a candidate tile or when some pixel's fp16-hi cost, widened
+// by its rounding, could exceed Lambda (then with every component of the
+// mixture). The argmax and the centred moments are accumulated online
 // (running maximum with rescaled, re-centred sums; the four lanes of a pixel
 // merge with a symmetric rule, so all of them hold bit-identical results).
-// Then the state update (a6) and the reflectivity / background MLE (a7).
+// Dense blocks are shared by the wavefronts of a workgroup (see the shared
+// blocks section). Then the state update (a6) and the reflectivity /
+// background MLE (a7).
 #include "r3d_device.hpp"
 #include "r3d_tile.hpp"
 
