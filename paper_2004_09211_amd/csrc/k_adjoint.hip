@@ -15,10 +15,11 @@
 //   dJ/dm_k    = sum_d g r_k (d-m_k) / V_k
 //   dJ/dV_k    = sum_d g r_k ((d-m_k)^2 - V_k) / (2 V_k^2)   (-> sigma_rw2 and v_k)
 //   dJ/dnu_k  += sum_d g r_k / nu_k.
-// One wavefront per pixel: pass 1 recomputes the moments over the candidate
-// depths (the same bound as the forward step: depths outside carry exactly
-// zero weight in fp32), pass 2 forms g(d), accumulates the sums and keeps g
-// in LDS, pass 3 correlates g with the non-empty bins for the tap sums. The
+// One wavefront per pixel, on the candidate depths of the forward step
+// (depths outside carry exactly zero weight in fp32): the frame's mean,
+// variance and log2 normaliser come from the forward step; pass 2 forms
+// g(d), accumulates the sums and keeps g in LDS, pass 3 correlates g with the
+// non-empty bins for the tap sums. The
 // adjoints of the neighbours' states are written per (component, pixel) and
 // gathered per neighbour by k_adjoint_gather, and the parameter sums are
 // reduced per block then over blocks in a fixed order: no atomics, so the
@@ -102,22 +103,10 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
   candidate_range(M, C, live, K, faulty, lane, R, Rl, dlo_c, dhi_c);
   const bool sparse = 3.f * K <= (float)M.T;
 
-  // ---- pass 1: moments of the pseudo-posterior ----
-  float Rm = -INFINITY, S0 = 0.f, S1 = 0.f, S2 = 0.f, ref = 0.f;
-  for (int d0 = dlo_c; d0 <= dhi_c; d0 += 64) {
-    unsigned cand, cmask;
-    chunk_masks(C, R, Rl, d0, cand, cmask);
-    if (cand == 0u) continue;
-    const int d = d0 + lane;
-    if (d > dhi_c) continue;
-    const float A = faulty ? 0.f : cost_gather(M, hist, nzmask, sh_h, d, sparse);
-    moment_push(fmaf(A, M.scale2, log_prior2(C, (float)d, live)), (float)d, Rm, ref, S0, S1, S2);
-  }
-  moment_merge_lanes(Rm, ref, S0, S1, S2);
-  const float mu = S1 / S0;
-  const float mean = ref + mu;
-  const float var = fmaxf(S2 / S0 - mu * mu, 0.f);
-  const float invS0 = 1.f / S0;
+  // the frame's moments and normaliser, as the forward step computed them
+  const float mean = io.mean[p];
+  const float var = io.var[p];
+  const float lz = io.lognorm[p];
 
   // ---- pass 2: g(d) and the sums ----
   const float mb = io.gm[p];
@@ -155,7 +144,7 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
       ssum += ek[k];
     }
     const float L2 = fmaf(A, M.scale2, mx + fast_log2(ssum));
-    const float w = fast_exp2(L2 - Rm) * invS0;
+    const float w = fast_exp2(L2 - lz);
     const float del = (float)d - mean;
     const float g = w * fmaf(mb, del, vb * fmaf(del, del, -var));
     gbuf[d - dlo_c] = g;

@@ -15,6 +15,8 @@ struct AdjIO {
   const int16_t* toa;
   const uint8_t* faulty;   // [P] or null
   const float *pm, *pv, *ppi;  // state before the frame
+  const float *mean, *var;     // [P] the frame's posterior mean and variance (the state after it)
+  const float* lognorm;        // [P] log2 of the frame's posterior normaliser (forward step)
   const float* gm;         // [P] adjoint of the frame's posterior mean
   const float* gv;         // [P] adjoint of the frame's posterior variance, or null
   float* cm;               // [9][P] adjoint of the previous mean of neighbour k of p

@@ -468,7 +468,7 @@ namespace {
 struct GradLayout {
   int N = 0, E = 0, nseg = 0, npar = 0;
   size_t P = 0, state_bytes = 0;
-  size_t ckpt = 0, seg = 0, am = 0, av = 0, cm = 0, cv = 0, pib = 0, bb = 0, part = 0;
+  size_t ckpt = 0, seg = 0, lnz = 0, am = 0, av = 0, cm = 0, cv = 0, pib = 0, bb = 0, part = 0;
   size_t bytes = 0;
   r3d::AdjGeom geo{};
 };
@@ -490,6 +490,7 @@ bool grad_layout(const r3d::DevModel& M, int N, int E, GradLayout& L) {
   };
   L.ckpt = take(L.nseg * L.state_bytes);
   L.seg = take((size_t)E * L.state_bytes);
+  L.lnz = take((size_t)E * L.P * sizeof(float));
   L.am = take(2 * L.P * sizeof(float));
   L.av = take(2 * L.P * sizeof(float));
   L.cm = take(9 * L.P * sizeof(float));
@@ -525,9 +526,10 @@ r3d_status check_frames(const r3d_frames* f) {
 }
 
 hipError_t forward_frame(const r3d::DevModel& M, const r3d_frames* f, int n, const r3d_state& prev,
-                         const r3d_state& next, hipStream_t s) {
+                         const r3d_state& next, hipStream_t s, float* lognorm = nullptr) {
   const float* pin = f->pi_in ? f->pi_in + (size_t)n * M.P : nullptr;
   r3d::StepIO io = make_io(pin, f->faulty, &prev, &next, nullptr);
+  io.lognorm = lognorm;
   io.row_ptr = f->row_ptr[n];
   io.toa = f->toa[n];
   return r3d::launch_step_plain(M, io, false, s);
@@ -604,16 +606,19 @@ r3d_status r3d_filter_backward(r3d_ctx* ctx, const r3d_frames* frames, int32_t c
     const int f0 = sg * L.E;
     const int f1 = std::min(N, f0 + L.E);
     const r3d_state ck = state_at(base, L.ckpt + sg * L.state_bytes, P);
-    // recompute the states after frames f0 .. f1-2 of the segment
+    // recompute the segment's frames: the state after each, and each
+    // frame's posterior normaliser (its moments are the state after it)
+    float* lnz = reinterpret_cast<float*>(base + L.lnz);
     r3d_state prev = ck;
-    for (int n = f0; n + 1 < f1 && e == hipSuccess; ++n) {
+    for (int n = f0; n < f1 && e == hipSuccess; ++n) {
       const r3d_state next = state_at(base, L.seg + (n - f0) * L.state_bytes, P);
-      e = forward_frame(M, frames, n, prev, next, s);
+      e = forward_frame(M, frames, n, prev, next, s, lnz + (size_t)(n - f0) * P);
       prev = next;
     }
     for (int n = f1 - 1; n >= f0 && e == hipSuccess; --n) {
       const r3d_state before =
           n == f0 ? ck : state_at(base, L.seg + (n - 1 - f0) * L.state_bytes, P);
+      const r3d_state after = state_at(base, L.seg + (n - f0) * L.state_bytes, P);
       r3d::AdjIO io{};
       io.row_ptr = frames->row_ptr[n];
       io.toa = frames->toa[n];
@@ -621,6 +626,9 @@ r3d_status r3d_filter_backward(r3d_ctx* ctx, const r3d_frames* frames, int32_t c
       io.pm = before.m;
       io.pv = before.v;
       io.ppi = before.pi;
+      io.mean = after.m;
+      io.var = after.v;
+      io.lognorm = lnz + (size_t)(n - f0) * P;
       io.gm = am[cur];
       io.gv = av[cur];
       io.cm = cm;

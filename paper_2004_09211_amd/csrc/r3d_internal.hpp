@@ -47,6 +47,7 @@ struct StepIO {
   float *nm, *nv, *npi, *nb;        // next state
   float *depth, *var, *intensity, *background, *pi0_next;
   int32_t* argmax;
+  float* lognorm;  // photon-list step only: log2 of the posterior's normaliser on the grid, or null
 };
 
 // launchers (one translation unit each)

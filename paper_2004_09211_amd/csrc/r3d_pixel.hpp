@@ -335,6 +335,7 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
     if (io.intensity) io.intensity[p] = r_hat;
     if (io.background) io.background[p] = b_hat;
     if (io.pi0_next) io.pi0_next[p] = pi0_next_at(M, io.pi_in, io.faulty, p);
+    if (io.lognorm) io.lognorm[p] = Rm + fast_log2(S0);  // log2 sum_d exp2(L(d))
   }
 }
 
