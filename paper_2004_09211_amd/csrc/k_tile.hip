@@ -533,30 +533,39 @@ __device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io,
 // flat or wide prior) can be shared by the wavefronts of its workgroup.
 // The dense block of the lowest-numbered wavefront owns the workgroup's share
 // region (a choice made by the data alone): its wavefront publishes the
-// margins and streams the block in chunks of pairs taken from the front; the
-// other wavefronts, once their own blocks are done, take chunks from the
-// back. Each chunk's moments go to a slot of their own and are merged in
-// chunk order, so the result does not depend on which wavefront took which
-// chunk.
+// margins and a list of the block's chunks of pairs: chunk 0 (its first
+// blocks are already in the owner's ring), the chunks holding candidate
+// pairs, then the others, each group in chunk order. The owner takes chunks
+// from the front of the list, so that it starts early on the chunks whose
+// evaluations dominate the time (a heavy chunk taken last would end the
+// workgroup late); the other wavefronts, once their own blocks are done,
+// take chunks from the back. Each chunk's moments go to a slot of their own
+// and are merged in chunk order, so the result does not depend on which
+// wavefront took which chunk.
 struct ShareLds {
   unsigned* ctl;  // [0] wavefronts decided, [1] owner wavefront + 1 (0: none),
-                  // [2] chunk claims (next front | end of the back << 16), [3] live components,
+                  // [2] chunk claims (next front | end of the back << 16, positions in the
+                  // list), [3] live components,
                   // [4 + w] wavefront w's decision (0: pending, 1: not dense, 2: dense)
   float* lam;     // [16] cost margin of each pixel
   unsigned* K;    // [16] photon count of each pixel (integer sums: exact in any order)
+  unsigned* order;  // [kMaxChunks] the list of chunks
+  unsigned* heavy;  // [kMaxChunks] chunk holds candidate pairs (1) or not (0)
   float* slot;    // [kMaxChunks][5][16] moments of each chunk
 };
 
 // control words: 4, then one decision per wavefront, padded to 8 words
 constexpr int kCtlWords = (4 + kTileWaves + 7) / 8 * 8;
-constexpr int kShareBytes = (kCtlWords + 32 + kMaxChunks * 5 * 16) * 4;
+constexpr int kShareBytes = (kCtlWords + 32 + 2 * kMaxChunks + kMaxChunks * 5 * 16) * 4;
 
 __device__ __forceinline__ ShareLds share_lds(const TileGeom& G, unsigned char* smem) {
   ShareLds S;
   S.ctl = reinterpret_cast<unsigned*>(smem + G.off_share);
   S.lam = reinterpret_cast<float*>(S.ctl + kCtlWords);
   S.K = S.ctl + kCtlWords + 16;
-  S.slot = reinterpret_cast<float*>(S.ctl + kCtlWords + 32);
+  S.order = S.ctl + kCtlWords + 32;
+  S.heavy = S.order + kMaxChunks;
+  S.slot = reinterpret_cast<float*>(S.heavy + kMaxChunks);
   return S;
 }
 
@@ -659,6 +668,30 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
         S.ctl[2] = 1u | ((unsigned)G.nchunks << 16);  // chunk 0 is the owner's
         S.ctl[3] = wave_live;
       }
+      // the list: lane k tests chunk k for candidate pairs, then places it
+      unsigned hk = 0u;
+      if (lane < G.nchunks) {
+        const int a = lane * G.chunk, b = min(a + G.chunk, G.npairs);
+        for (int w = a >> 5; w <= (b - 1) >> 5; ++w) {
+          const int lo = max(a - 32 * w, 0), hi = min(b - 32 * w, 32);
+          const unsigned msk = (hi == 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+          hk |= (B.pmask[w] & msk) != 0u ? 1u : 0u;
+        }
+        S.heavy[lane] = hk;
+      }
+      wave_sync();
+      if (lane < G.nchunks) {
+        // position: chunk 0 first, then (heavy first, chunk index)
+        int pos = 0;
+        if (lane > 0) {
+          pos = 1;
+          for (int j = 1; j < G.nchunks; ++j) {
+            const unsigned hj = S.heavy[j];
+            pos += (hj > hk || (hj == hk && j < lane)) ? 1 : 0;
+          }
+        }
+        S.order[pos] = (unsigned)lane;
+      }
       // the owner's ring runs on from one chunk into the next (kb_end stays
       // at the end of the block)
       c = 0;
@@ -669,8 +702,9 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   int nactive = 0;
   for (int w = 0; w < NW; ++w) nactive += (w * ngrp + (int)blockIdx.x < G.nblk) ? 1 : 0;
 
-  // take a chunk of the shared block: the owner from the front, the others
-  // from the back (-1 once the two ends meet); each chunk is taken once
+  // take a chunk of the shared block: the owner from the front of the list,
+  // the others from the back (-1 once the two ends meet); each chunk is
+  // taken once
   auto claim = [&](bool front) __attribute__((always_inline)) -> int {
     int got = -1;
     if (lane == 0) {
@@ -680,7 +714,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
         if (f >= b) break;
         const unsigned seen = atomicCAS(&S.ctl[2], old, front ? old + 1u : old - 0x10000u);
         if (seen == old) {
-          got = front ? (int)f : (int)b - 1;
+          got = (int)S.order[front ? f : b - 1u];
           break;
         }
         old = seen;
@@ -706,6 +740,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   // first: the task is the wavefront's own block, whose first ring blocks
   // are already loaded (a wavefront without a block starts with a chunk)
   bool have = active, first = active, helping = false;
+  int pend = -1;  // a chunk the owner took that does not follow its ring
   for (;;) {
     if (have) {
       if (!first) {
@@ -831,10 +866,11 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
           account(load_block(M, L, g, kb));
         }
       }
-      // the owner's own task runs through its chunks without reloading the
-      // ring: at each chunk end (chunks are whole ring rounds) it flushes and
-      // takes the next chunk from the front
-      const bool run_on = owner && first;
+      // the owner runs on through chunks that follow each other in the list
+      // without reloading the ring: at each chunk end (chunks are whole ring
+      // rounds) it flushes and takes the next chunk from the front; one that
+      // does not follow becomes its next task
+      const bool run_on = owner;
       bool flushed = false;
       for (int m0 = mb; m0 < me; m0 += RING) {
         // candidate-pair bits of pairs m0 .. m0 + RING - 1 (< 41 bits past
@@ -919,11 +955,12 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
         if (run_on && m0 + RING == me && me < G.npairs) {
           flush(c);
           const int nc = claim(true);
-          if (nc < 0) {
+          if (nc != c + 1) {
             flushed = true;
+            pend = nc;
             break;
           }
-          c = nc;  // == c + 1: the chunks taken from the front are consecutive
+          c = nc;
           me = me + G.chunk < G.npairs ? me + G.chunk : G.npairs;
         }
       }
@@ -933,9 +970,8 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
       if (!flushed) flush(c);
       first = false;
     }
-    if (!helping) {
+    if (!helping && !owner) {
       helping = true;
-      if (owner) break;  // its chunks were taken in its own task
       // wait (bounded) until every wavefront with a block has decided; a
       // wavefront that gives up leaves the chunks to the others, which take
       // all of them
@@ -953,11 +989,13 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
       thr = margin_bits(S.lam[i16]);
       wave_live = __builtin_amdgcn_readfirstlane(S.ctl[3]);
     }
-    c = claim(false);
+    c = pend >= 0 ? pend : claim(owner);
+    pend = -1;
     if (c < 0) break;
     mb = c * G.chunk;
     me = mb + G.chunk < G.npairs ? mb + G.chunk : G.npairs;
-    kb_end = G.kbA0 + me + NBP - 2;
+    // the owner's ring may run on into the next chunk: it loads to the end
+    kb_end = owner ? G.kb_last : G.kbA0 + me + NBP - 2;
     have = true;
   }
   __syncthreads();
