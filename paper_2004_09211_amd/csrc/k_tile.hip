@@ -334,12 +334,13 @@ __device__ __forceinline__ BlockLds block_lds(const TileGeom& G, unsigned char* 
 // region; returns the lane's cost margin Lambda (log2 units) and the
 // components live for some pixel (wave-uniform). after_gather() is called
 // once the state and reference-cost loads are issued (the caller's first
-// histogram loads then queue behind them).
-template <int kEng, int NBP, typename AfterGather>
+// histogram loads then queue behind them), after_masks() once the candidate
+// masks are complete.
+template <int kEng, int NBP, typename AfterGather, typename AfterMasks>
 __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, const StepIO& io,
                                           LanePix& L, const float* sh_h, const BlockLds& B,
                                           int lane, float& Lam, unsigned& wave_live,
-                                          AfterGather&& after_gather) {
+                                          AfterGather&& after_gather, AfterMasks&& after_masks) {
   constexpr bool kMfma = kEng != kEngValu;
   constexpr bool kSplit = kEng == kEngMfma16x2;
   // taps per lane (j = g + 4 u): W <= 32 NBP - 30 by construction of NBP, so u < 8 NBP - 7
@@ -446,6 +447,8 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
       set_bits(B.pmask, ta >> 1, tb >> 1);
     }
   }
+  wave_sync();
+  after_masks();
   // the reference cost, whose gather has been in flight meanwhile
   float lref = 0.f;
 #pragma unroll
@@ -531,22 +534,24 @@ __device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io,
 // ============================ shared blocks ============================
 // A dense block (candidate tiles on many of its pairs: a frame border, a
 // flat or wide prior) can be shared by the wavefronts of its workgroup.
-// The dense block of the lowest-numbered wavefront owns the workgroup's share
+// The dense block with the most candidate pairs owns the workgroup's share
 // region (a choice made by the data alone): its wavefront publishes the
 // margins and a list of the block's chunks of pairs: chunk 0 (its first
-// blocks are already in the owner's ring), the chunks holding candidate
-// pairs, then the others, each group in chunk order. The owner takes chunks
-// from the front of the list, so that it starts early on the chunks whose
-// evaluations dominate the time (a heavy chunk taken last would end the
-// workgroup late); the other wavefronts, once their own blocks are done,
-// take chunks from the back. Each chunk's moments go to a slot of their own
-// and are merged in chunk order, so the result does not depend on which
-// wavefront took which chunk.
+// blocks are already in the owner's ring), the heavy chunks (those holding
+// candidate pairs, whose evaluations dominate the time), then the light
+// ones, each group in chunk order. The owner takes chunks from the front of
+// the list; the other wavefronts, once their own blocks are done, take the
+// heavy chunks left from the back of the heavy part, then light ones from
+// the back of the list, so that no heavy chunk is left for last. Each
+// chunk's moments go to a slot of their own and are merged in chunk order,
+// so the result does not depend on which wavefront took which chunk.
 struct ShareLds {
   unsigned* ctl;  // [0] wavefronts decided, [1] owner wavefront + 1 (0: none),
-                  // [2] chunk claims (next front | end of the back << 16, positions in the
-                  // list), [3] live components,
-                  // [4 + w] wavefront w's decision (0: pending, 1: not dense, 2: dense)
+                  // [2] chunk claims, positions in the list (owner's next | end of the
+                  // others' heavy part << 8 | end of the others' light part << 16 |
+                  // end of the heavy part << 24), [3] live components,
+                  // [4 + w] wavefront w's decision (0: pending, 1: not dense, 2 + its
+                  // candidate pairs: dense)
   float* lam;     // [16] cost margin of each pixel
   unsigned* K;    // [16] photon count of each pixel (integer sums: exact in any order)
   unsigned* order;  // [kMaxChunks] the list of chunks
@@ -625,37 +630,50 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   }
   float Lam = 0.f;
   unsigned wave_live = 0u;
-  // the first blocks are in flight while the prior is prepared
+  // the first blocks are in flight while the prior is prepared; the block's
+  // decision (below) is published as soon as its candidate masks are built
+  bool dense = false;
+  unsigned mine = 1u;
   if (active)
-    step_prep<kEng, NBP>(M, G, io, L, sh_h, B, lane, Lam, wave_live, [&]() __attribute__((always_inline)) {
+    step_prep<kEng, NBP>(
+        M, G, io, L, sh_h, B, lane, Lam, wave_live,
+        [&]() __attribute__((always_inline)) {
 #pragma unroll
-      for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + x);
-    });
+          for (int x = 0; x < RING - 1; ++x) ring[x] = fetch(G.kbA0 + x);
+        },
+        [&]() __attribute__((always_inline)) {
+          int ncand = 0;
+          for (int w = 0; w < G.pair_words; ++w)
+            ncand += __builtin_popcount(__builtin_amdgcn_readfirstlane(B.pmask[w]));
+          dense = G.nchunks >= 2 && 32 * ncand >= G.npairs;
+          // decision: 1 for a plain block, 2 + its candidate pairs for a dense one
+          mine = dense ? 2u + (unsigned)ncand : 1u;
+          if (lane == 0)
+            __hip_atomic_store(&S.ctl[4 + wave], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        });
   const bool own_faulty = L.faulty;
-  // a dense block (candidate tiles on at least a 32nd of its pairs: most
-  // blocks but the plainest) is shared when no lower-numbered wavefront has
-  // one, so that the workgroup's wavefronts end together: a dense wavefront
-  // waits (bounded) for the decisions of the lower ones, which finish their
-  // preparation at about the same time. The owner publishes the margins,
-  // then every wavefront with a block counts itself decided.
+  // of the dense blocks (candidate tiles on at least a 32nd of their pairs:
+  // most blocks but the plainest) the one with the most candidate pairs (the
+  // lowest-numbered wavefront's among equals) is shared, so that the
+  // workgroup's wavefronts end together: a dense wavefront waits (bounded)
+  // for the decisions of the others, which finish their preparation at about
+  // the same time. The owner publishes the margins, then every wavefront
+  // with a block counts itself decided.
   bool owner = false;
   if (active) {
-    int ncand = 0;
-    for (int w = 0; w < G.pair_words; ++w)
-      ncand += __builtin_popcount(__builtin_amdgcn_readfirstlane(B.pmask[w]));
-    const bool dense = G.nchunks >= 2 && 32 * ncand >= G.npairs;
-    if (lane == 0)
-      __hip_atomic_store(&S.ctl[4 + wave], dense ? 2u : 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (dense) {
       owner = true;
-      for (int v = 0; v < wave && owner; ++v) {
+      for (int v = 0; v < NW && owner; ++v) {
+        if (v == wave || v * ngrp + (int)blockIdx.x >= G.nblk) continue;  // itself, or no block
         unsigned dv = 0u;
         for (int n = 0; n < (1 << 20) && dv == 0u; ++n) {
           dv = __builtin_amdgcn_readfirstlane(
               __hip_atomic_load(&S.ctl[4 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
           if (dv == 0u) __builtin_amdgcn_s_sleep(4);
         }
-        owner = dv == 1u;  // a lower dense block (or no answer) keeps this one unshared
+        // a denser block, an as dense lower-numbered one, or no answer keeps
+        // this one unshared
+        owner = dv != 0u && (dv < mine || (dv == mine && v > wave));
       }
     }
     if (owner) {
@@ -665,7 +683,6 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
       }
       if (lane == 0) {
         S.ctl[1] = (unsigned)wave + 1u;
-        S.ctl[2] = 1u | ((unsigned)G.nchunks << 16);  // chunk 0 is the owner's
         S.ctl[3] = wave_live;
       }
       // the list: lane k tests chunk k for candidate pairs, then places it
@@ -692,6 +709,10 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
         }
         S.order[pos] = (unsigned)lane;
       }
+      // the list's heavy part is [0, nh); chunk 0 is the owner's
+      const unsigned nh =
+          1u + (unsigned)__builtin_popcountll(__ballot(lane >= 1 && lane < G.nchunks && hk != 0u));
+      if (lane == 0) S.ctl[2] = 1u | (nh << 8) | ((unsigned)G.nchunks << 16) | (nh << 24);
       // the owner's ring runs on from one chunk into the next (kb_end stays
       // at the end of the block)
       c = 0;
@@ -702,19 +723,30 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
   int nactive = 0;
   for (int w = 0; w < NW; ++w) nactive += (w * ngrp + (int)blockIdx.x < G.nblk) ? 1 : 0;
 
-  // take a chunk of the shared block: the owner from the front of the list,
-  // the others from the back (-1 once the two ends meet); each chunk is
-  // taken once
+  // take a chunk of the shared block (-1 once none is left; each chunk is
+  // taken once): while heavy ones are left, the owner from the front of the
+  // list and the others from the back of its heavy part; then the owner from
+  // the front of the light part and the others from the back of the list
   auto claim = [&](bool front) __attribute__((always_inline)) -> int {
     int got = -1;
     if (lane == 0) {
       unsigned old = __hip_atomic_load(&S.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       for (;;) {
-        const unsigned f = old & 0xffffu, b = old >> 16;
-        if (f >= b) break;
-        const unsigned seen = atomicCAS(&S.ctl[2], old, front ? old + 1u : old - 0x10000u);
+        const unsigned f = old & 0xffu, hb = (old >> 8) & 0xffu, b = (old >> 16) & 0xffu,
+                       nh = old >> 24;
+        unsigned pos, next;
+        if (f < hb) {
+          pos = front ? f : hb - 1u;
+          next = front ? old + 1u : old - 0x100u;
+        } else {
+          const unsigned f2 = f > nh ? f : nh;
+          if (f2 >= b) break;
+          pos = front ? f2 : b - 1u;
+          next = front ? ((old & ~0xffu) | (f2 + 1u)) : old - 0x10000u;
+        }
+        const unsigned seen = atomicCAS(&S.ctl[2], old, next);
         if (seen == old) {
-          got = (int)S.order[front ? f : b - 1u];
+          got = (int)S.order[pos];
           break;
         }
         old = seen;
