@@ -848,14 +848,19 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
           mo.ref = dnew;
         }
         if (mt > -INFINITY) {
+          // the four depths d0 + q in closed form: with e0 = d0 - ref and
+          // T_k = sum_q q^k w_q, sum_q w_q e_q = e0 T0 + T1 and
+          // sum_q w_q e_q^2 = e0 (e0 T0 + 2 T1) + T2
+          float w[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float wq = fast_exp2(Lq[q] - mo.R);
-            const float e = (float)(dbase + q) - mo.ref;
-            mo.S0 += wq;
-            mo.S1 = fmaf(e, wq, mo.S1);
-            mo.S2 = fmaf(e * e, wq, mo.S2);
-          }
+          for (int q = 0; q < 4; ++q) w[q] = fast_exp2(Lq[q] - mo.R);
+          const float T0 = (w[0] + w[1]) + (w[2] + w[3]);
+          const float T1 = fmaf(3.f, w[3], fmaf(2.f, w[2], w[1]));
+          const float T2 = fmaf(9.f, w[3], fmaf(4.f, w[2], w[1]));
+          const float e0 = (float)dbase - mo.ref;
+          mo.S0 += T0;
+          mo.S1 += fmaf(e0, T0, T1);
+          mo.S2 += fmaf(e0, fmaf(e0, T0, 2.f * T1), T2);
         }
       };
 
