@@ -645,14 +645,14 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
           int ncand = 0;
           for (int w = 0; w < G.pair_words; ++w)
             ncand += __builtin_popcount(__builtin_amdgcn_readfirstlane(B.pmask[w]));
-          dense = G.nchunks >= 2 && 32 * ncand >= G.npairs;
+          dense = G.nchunks >= 2 && 64 * ncand >= G.npairs;
           // decision: 1 for a plain block, 2 + its candidate pairs for a dense one
           mine = dense ? 2u + (unsigned)ncand : 1u;
           if (lane == 0)
             __hip_atomic_store(&S.ctl[4 + wave], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         });
   const bool own_faulty = L.faulty;
-  // of the dense blocks (candidate tiles on at least a 32nd of their pairs:
+  // of the dense blocks (candidate tiles on at least a 64th of their pairs:
   // most blocks but the plainest) the one with the most candidate pairs (the
   // lowest-numbered wavefront's among equals) is shared, so that the
   // workgroup's wavefronts end together: a dense wavefront waits (bounded)
