@@ -60,7 +60,7 @@ constexpr int kHaloBytes = 448;         // 6x6 halo of (m, v, pi), 108 floats
 constexpr int kCompBytes = 9 * 16 * 16;  // (m, k2, w2, 0) of 9 components x 16 pixels
 
 // blocks in flight per wavefront, beyond the blocks of the current pair
-template <int kEng> constexpr int kTilePF = kEng == kEngValu ? 3 : 6;
+template <int kEng> constexpr int kTilePF = kEng == kEngValu ? 3 : 5;
 // wavefronts per workgroup of the step (the vector-FMA engine keeps an LDS
 // ring per wavefront, so it stays at 4)
 template <int kEng> constexpr int kWavesOf = kEng == kEngValu ? 4 : kTileWaves;
