@@ -9,8 +9,9 @@ paper (cited in its docstring) and is written so that it can be checked
 against that passage by eye.
 """
 from .r3d_oracle import (  # noqa: F401
-    Model, State, validate, histogram, modified_irf, cost_from_histogram,
-    cost_from_photons, flat_component, prior_components, log_prior,
+    Model, State, validate, histogram, modified_irf, correlation, cost_from_histogram,
+    cost_from_histogram_pirf, cost_from_photons, flat_component, prior_components, log_prior,
     posterior_moments, background_intensity, pi0_next, init_state, step, run,
-    gaussian_irf_sigma, filter_loss, filter_loss_grad_fd,
+    gaussian_irf_sigma, filter_loss, filter_loss_grad_fd, argmax_with_margin,
+    min_divergence, msl_objective, msl_min_divergence,
 )

@@ -131,19 +131,51 @@ def modified_irf(irf: np.ndarray, beta: float) -> np.ndarray:
     return np.asarray(irf, dtype=np.float64) ** beta
 
 
-def cost_from_histogram(z: np.ndarray, model: Model) -> np.ndarray:
-    """Log pseudo-likelihood on the depth grid, histogram form:
-    ell(d) = -K * CE_beta(d) = (beta+1)/beta * sum_j irf[j]^beta z[d-c+j],
-    with z = 0 outside [0, T). Returns [n, D]."""
+def correlation(z: np.ndarray, model: Model) -> np.ndarray:
+    """Cross-correlation of the histogram with the modified IRF on the depth
+    grid (Sec. II-B: z^T s_d^beta): sum_j irf[j]^beta z[d-c+j], with z = 0
+    outside [0, T). Returns [n, D]."""
     h = modified_irf(model.irf, model.beta)
-    scale = (model.beta + 1.0) / model.beta
     z = np.asarray(z, dtype=np.float64)
     d = model.d_lo + np.arange(model.D)
-    ell = np.zeros((z.shape[0], model.D))
+    corr = np.zeros((z.shape[0], model.D))
     for j in range(model.W):
         t = d - model.c + j
         ok = (t >= 0) & (t < model.T)
-        ell[:, ok] += h[j] * z[:, t[ok]]
+        corr[:, ok] += h[j] * z[:, t[ok]]
+    return corr
+
+
+def cost_from_histogram(z: np.ndarray, model: Model) -> np.ndarray:
+    """Log pseudo-likelihood on the depth grid, histogram form:
+    ell(d) = -K * CE_beta(d) = (beta+1)/beta * sum_j irf[j]^beta z[d-c+j]
+    (eq. beta_CE; the correlation above times (beta+1)/beta). Returns [n, D]."""
+    scale = (model.beta + 1.0) / model.beta
+    return scale * correlation(z, model)
+
+
+def cost_from_histogram_pirf(z: np.ndarray, model: Model, irf_pix: np.ndarray,
+                             c_pix: Optional[np.ndarray] = None) -> np.ndarray:
+    """The same cost with a pixel-dependent IRF (Sec. II-A: the method also
+    applies when the shape of the IRF depends on the pixel): row i of
+    ``irf_pix`` ([n, W]) and tap ``c_pix[i]`` (default the model's c) are the
+    IRF of the pixel of row i of ``z``; ell_i(d) = (beta+1)/beta *
+    sum_j irf_pix[i, j]^beta z_i[d - c_i + j]. Returns [n, D]."""
+    z = np.asarray(z, dtype=np.float64)
+    irf_pix = np.asarray(irf_pix, dtype=np.float64)
+    n, W = irf_pix.shape
+    if z.shape[0] != n:
+        raise ValueError("one IRF per histogram row")
+    c_pix = np.full(n, model.c) if c_pix is None else np.asarray(c_pix, dtype=np.int64)
+    h = irf_pix ** model.beta
+    scale = (model.beta + 1.0) / model.beta
+    d = model.d_lo + np.arange(model.D)
+    ell = np.zeros((n, model.D))
+    for i in range(n):
+        for j in range(W):
+            t = d - c_pix[i] + j
+            ok = (t >= 0) & (t < model.T)
+            ell[i, ok] += h[i, j] * z[i, t[ok]]
     return scale * ell
 
 
@@ -254,7 +286,8 @@ def posterior_moments(ell: np.ndarray, logf: np.ndarray, grid: np.ndarray) -> di
 # a7: background and reflectivity (Sec. II-E, eq. lik_bg_poisson)
 # ---------------------------------------------------------------------------
 def background_intensity(z: np.ndarray, model: Model, d_star: np.ndarray,
-                         detected: np.ndarray):
+                         detected: np.ndarray, irf_pix: Optional[np.ndarray] = None,
+                         c_pix: Optional[np.ndarray] = None):
     """Undetected pixel: b = K / T and r = 0. Detected pixel: maximum
     likelihood (r, b) of z_t ~ Poisson(r s_t + b), s_t = irf[t - d* + c]
     (zero outside the taps), r, b >= 0.
@@ -263,7 +296,9 @@ def background_intensity(z: np.ndarray, model: Model, d_star: np.ndarray,
     so the optimum lies on b(r) = (K - r S) / T, r in [0, K/S]. The
     log-likelihood restricted to that segment is concave; its derivative
     phi'(r) = sum_t z_t (s_t - S/T) / (r s_t + b(r)) is decreasing and is
-    bisected to float64 resolution. r = 0 when phi'(0) <= 0."""
+    bisected to float64 resolution. r = 0 when phi'(0) <= 0. With
+    ``irf_pix`` ([n, W]) and ``c_pix`` the IRF of each row's pixel is its own
+    (Sec. II-A, pixel-dependent IRF)."""
     z = np.asarray(z, dtype=np.float64)
     n, T = z.shape
     K = z.sum(axis=1)
@@ -271,10 +306,12 @@ def background_intensity(z: np.ndarray, model: Model, d_star: np.ndarray,
     b_hat = K / T
     t = np.arange(T)
     for i in np.nonzero(np.asarray(detected) & (K > 0))[0]:
-        tap = t - int(d_star[i]) + model.c
-        inwin = (tap >= 0) & (tap < model.W)
+        irf_i = model.irf if irf_pix is None else np.asarray(irf_pix[i], dtype=np.float64)
+        c_i = model.c if c_pix is None else int(c_pix[i])
+        tap = t - int(d_star[i]) + c_i
+        inwin = (tap >= 0) & (tap < irf_i.shape[0])
         s = np.zeros(T)
-        s[inwin] = model.irf[tap[inwin]]
+        s[inwin] = irf_i[tap[inwin]]
         S = s.sum()
         if S <= 0:
             continue
@@ -343,15 +380,20 @@ def init_state(model: Model) -> State:
 
 def step(model: Model, state: State, z: np.ndarray, pixels=None,
          pi_in: Optional[np.ndarray] = None,
-         faulty: Optional[np.ndarray] = None):
+         faulty: Optional[np.ndarray] = None,
+         irf_pix: Optional[np.ndarray] = None,
+         c_pix: Optional[np.ndarray] = None):
     """One frame of Algorithm 1 for the pixels in ``pixels`` (default all).
 
     ``z`` holds the histograms of exactly those pixels ([n, T]). ``pi_in``
     (length P, default all ones) is the presence probability of the current
     frame supplied by the detector; ``faulty`` (length P bool) marks pixels
     without observations: their pseudo-posterior is the prior and their
-    presence probability 0.5 (Sec. III-B, last paragraph). Returns the new
-    state (NaN outside ``pixels``) and a dict of per-pixel outputs.
+    presence probability 0.5 (Sec. III-B, last paragraph). ``irf_pix``
+    ([P, W], with ``c_pix`` [P] or the model's c) gives every pixel an IRF of
+    its own (Sec. II-A): the cost and the background / reflectivity estimate
+    then use the pixel's IRF. Returns the new state (NaN outside ``pixels``)
+    and a dict of per-pixel outputs.
     """
     validate(model)
     P = model.P
@@ -367,12 +409,18 @@ def step(model: Model, state: State, z: np.ndarray, pixels=None,
 
     logw, mean, var = prior_components(model, state, pixels)
     logf = log_prior(logw, mean, var, grid)
-    ell = cost_from_histogram(z, model)
+    if irf_pix is None:
+        ell = cost_from_histogram(z, model)
+        irf_sel = c_sel = None
+    else:
+        irf_sel = np.asarray(irf_pix, dtype=np.float64)[pixels]
+        c_sel = None if c_pix is None else np.asarray(c_pix, dtype=np.int64)[pixels]
+        ell = cost_from_histogram_pirf(z, model, irf_sel, c_sel)
     ell[fault] = 0.0
     post = posterior_moments(ell, logf, grid)
     detected = pi_now[pixels] > 0.5
     zz = np.where(fault[:, None], 0, z)
-    r_hat, b_hat = background_intensity(zz, model, post["d_star"], detected)
+    r_hat, b_hat = background_intensity(zz, model, post["d_star"], detected, irf_sel, c_sel)
     b_hat = np.where(fault, state.b[pixels], b_hat)
 
     new = State(np.full(P, np.nan), np.full(P, np.nan), np.full(P, np.nan),
@@ -405,6 +453,73 @@ def run(model: Model, frames, state: Optional[State] = None, pi_in=None,
         st, o = step(model, st, z, pi_in=pin, faulty=faulty)
         outs.append(o)
     return st, outs
+
+
+# ---------------------------------------------------------------------------
+# minimum-divergence (pseudo-ML) estimates: the cost alone, no prior
+# (Sec. II-B, last paragraph; Appendix, eq. div_MSL)
+# ---------------------------------------------------------------------------
+def argmax_with_margin(J: np.ndarray) -> dict:
+    """First maximiser of each row of J, its value and its margin over the
+    best other grid point (inf for a single point)."""
+    J = np.asarray(J, dtype=np.float64)
+    n = J.shape[0]
+    rows = np.arange(n)
+    i = np.argmax(J, axis=1)
+    v = J[rows, i]
+    if J.shape[1] > 1:
+        J2 = J.copy()
+        J2[rows, i] = -np.inf
+        margin = v - J2.max(axis=1)
+    else:
+        margin = np.full(n, np.inf)
+    return dict(index=i, value=v, margin=margin)
+
+
+def min_divergence(z: np.ndarray, model: Model) -> dict:
+    """Minimum beta-divergence depth estimate of each pixel: minimising
+    eq. beta_div2 over the depth grid, i.e. maximising the histogram
+    cross-correlation ell(d) of Sec. II-B with no prior. Returns the first
+    maximiser (grid index and depth), ell there (natural log units, as
+    cost_from_histogram) and its margin over the runner-up."""
+    r = argmax_with_margin(cost_from_histogram(z, model))
+    r["d_hat"] = model.d_lo + r["index"]
+    return r
+
+
+def msl_objective(z_bands, models) -> np.ndarray:
+    """Multispectral beta-divergence (Appendix, eq. div_MSL): the divergence
+    is Const - (beta+1)/beta * prod_l (1/K_l) sum_k f_l(y_lk | d)^beta, so its
+    minimiser maximises prod_l c_l(d) / K_l with c_l the band's histogram
+    correlation with irf_l^beta. Returns sum_l [log c_l(d) - log K_l], [n, D]
+    (-inf where some band's correlation vanishes). The bands share T, the
+    depth grid and beta; each has its own IRF and peak tap. A band without
+    photons (K_l = 0) has no empirical distribution and is left out."""
+    if len(z_bands) != len(models) or not models:
+        raise ValueError("one model per band")
+    m0 = models[0]
+    for m in models:
+        if (m.T, m.d_lo, m.D, m.beta) != (m0.T, m0.d_lo, m0.D, m0.beta):
+            raise ValueError("bands must share T, the depth grid and beta")
+    n = np.asarray(z_bands[0]).shape[0]
+    J = np.zeros((n, m0.D))
+    for zb, m in zip(z_bands, models):
+        zb = np.asarray(zb, dtype=np.float64)
+        K = zb.sum(axis=1)
+        corr = correlation(zb, m)
+        with np.errstate(divide="ignore"):
+            term = np.log(corr) - np.log(np.where(K > 0, K, 1.0))[:, None]
+        J += np.where((K > 0)[:, None], term, 0.0)
+    return J
+
+
+def msl_min_divergence(z_bands, models) -> dict:
+    """Minimum multispectral beta-divergence depth of each pixel (Appendix,
+    eq. div_MSL; the estimator compared there). First maximiser of
+    msl_objective, its value and margin."""
+    r = argmax_with_margin(msl_objective(z_bands, models))
+    r["d_hat"] = models[0].d_lo + r["index"]
+    return r
 
 
 # ---------------------------------------------------------------------------
