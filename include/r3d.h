@@ -34,8 +34,9 @@
  * time.
  * Errors: parameter and shape errors are returned synchronously before any
  * launch. Data-dependent faults found by a kernel (a ToA outside [0, T), an
- * fp16 count above 2048 or negative) set the context's device error word, read
- * back by r3d_last_device_status; the affected outputs are then undefined.
+ * fp16 count that is not an integer in [0, 2048] or has its sign bit set, an
+ * invalid per-pixel IRF) set the context's device error word, read back by
+ * r3d_last_device_status; the affected outputs are then undefined.
  */
 #ifndef R3D_H
 #define R3D_H
@@ -51,7 +52,7 @@ typedef enum {
     R3D_OK = 0,
     R3D_EINVAL = -1,        /* bad parameter, shape or NULL pointer             */
     R3D_ERANGE = -2,        /* a ToA outside [0, T) (device-detected)           */
-    R3D_EOVERFLOW = -3,     /* an fp16 count > 2048 or < 0 (device-detected)    */
+    R3D_EOVERFLOW = -3,     /* an fp16 count not an integer in [0, 2048], or -0 */
     R3D_ENOMEM = -4,        /* device allocation failed                         */
     R3D_EHIP = -5,          /* a HIP runtime call failed                        */
     R3D_EUNSUPPORTED = -6,  /* size or option outside what the kernels support  */
@@ -104,19 +105,25 @@ typedef struct {
 } r3d_out;
 
 /* Create a context on the current HIP device: validates the parameters,
- * uploads irf and irf^beta. Synchronous. Returns R3D_EINVAL on a bad
- * parameter (beta <= 0, sigma_rw2 <= 0, W out of range, c outside [0, W),
- * negative or all-zero irf or nu, d_max <= d_min, empty sizes). */
+ * uploads irf and the modified IRF irf^beta of Sec. II-B (the taps the
+ * cost correlates with the histogram). Synchronous. Returns R3D_EINVAL on
+ * a bad parameter (beta <= 0 (Sec. II-B requires beta > 0), sigma_rw2 <= 0,
+ * W out of range, c outside [0, W), negative or all-zero irf or nu,
+ * d_max <= d_min, empty sizes, d_lo outside [-2^20, 2^20]). */
 r3d_status r3d_create(const r3d_params *params, r3d_ctx **out);
 
-/* Destroy a context (synchronises the device first). NULL is ignored. */
+/* Destroy a context and free its device memory (synchronises the device
+ * first). NULL is ignored. */
 void r3d_destroy(r3d_ctx *ctx);
 
-/* Initial state of Algorithm 1 (left open by the paper): every pixel flat,
- * m = (d_min+d_max)/2, v = (d_max-d_min)^2/12, pi = 0.5, b = 0. */
+/* Initial state of Algorithm 1 (Sec. III-B, its initialisation of q and of
+ * the presence probabilities, whose values the paper leaves open): every
+ * pixel flat, m = (d_min+d_max)/2, v = (d_max-d_min)^2/12 (the flat
+ * Gaussian of Sec. III-A), pi = 0.5, b = 0. st: four device arrays of P. */
 r3d_status r3d_state_init(r3d_ctx *ctx, const r3d_state *st, void *stream);
 
-/* a1 alone: per-pixel photon-count histogram of a CSR photon list, written as
+/* a1 alone: per-pixel photon-count histogram of a CSR photon list (Sec. II-A:
+ * z_t counts the pixel's ToAs in bin t, eq. lik_ideal_poisson), written as
  * fp16 [P][T] (IEEE binary16 bits). row_ptr: int32[P+1], non-decreasing,
  * row_ptr[0] = 0; toa: int16[row_ptr[P]], any order inside a pixel. Counts
  * are exact up to 2048; a larger count sets R3D_EOVERFLOW, a ToA outside
@@ -124,9 +131,11 @@ r3d_status r3d_state_init(r3d_ctx *ctx, const r3d_state *st, void *stream);
 r3d_status r3d_histogram(r3d_ctx *ctx, const int32_t *row_ptr, const int16_t *toa,
                          uint16_t *hist, void *stream);
 
-/* a3 alone, for inspection and tests: ell(d) for npix pixels of an fp16
- * histogram [npix][T], written as float [npix][D] in natural-log units, with
- * the context's precision. */
+/* a3 alone, for inspection and tests: the log pseudo-likelihood
+ * ell(d) = (beta+1)/beta * sum_j irf[j]^beta z[d-c+j] (Sec. II-B, histogram
+ * form of eq. beta_div2; Sec. II-C, eq. beta_CE) for npix pixels of an fp16
+ * histogram [npix][T] (device), written as float [npix][D] (device) in
+ * natural-log units, with the context's precision. */
 r3d_status r3d_cost(r3d_ctx *ctx, const uint16_t *hist, int32_t npix, float *ell,
                     void *stream);
 
@@ -168,9 +177,65 @@ r3d_status r3d_run_hist(r3d_ctx *ctx, const uint16_t *const *hist, int32_t nfram
                         const float *pi_in, const uint8_t *faulty, const r3d_state *state,
                         const r3d_out *out, void *stream);
 
-/* Synchronise the stream, then read and clear the device error word:
- * R3D_OK, R3D_ERANGE or R3D_EOVERFLOW (the first kind recorded). */
+/* Synchronise the stream, then read and clear the device error word: the
+ * data checks of the calls above (a ToA outside the timing window (0, T) of
+ * Sec. II-A: R3D_ERANGE; a histogram count that is not an integer in
+ * [0, 2048]: R3D_EOVERFLOW; an invalid per-pixel IRF: R3D_EINVAL). Returns
+ * R3D_OK or the first kind recorded. */
 r3d_status r3d_last_device_status(r3d_ctx *ctx, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Minimum-divergence (pseudo-ML) depth estimates: the cost alone, no prior.
+ * ------------------------------------------------------------------------- */
+
+/* Minimum beta-divergence depth of each pixel (Sec. II-B, last paragraph:
+ * eq. beta_div2 minimised over d without prior information, i.e. the depth
+ * maximising the histogram correlation ell(d)). hist: device fp16 [P][T]
+ * (integer counts in [0, 2048], 16-byte aligned, T a multiple of 8).
+ * argmax: device int32 [P], the first grid depth of the maximum (d_lo when
+ * ell vanishes everywhere); value: device float [P] or NULL, ell there in
+ * natural-log units. Evaluated with the context's precision. Asynchronous;
+ * count errors set R3D_EOVERFLOW in the device error word. */
+r3d_status r3d_min_divergence(r3d_ctx *ctx, const uint16_t *hist, int32_t *argmax, float *value,
+                              void *stream);
+
+/* Minimum multispectral beta-divergence depth of each pixel (Appendix,
+ * eq. div_MSL): maximises sum over bands of log(c_l(d) / K_l), c_l the
+ * correlation of band l's histogram with its own irf_l^beta and K_l its
+ * photon count; bands without photons are left out. bands: HOST array of
+ * nbands contexts (1 <= nbands <= 4), one per band with its own IRF and peak
+ * tap, sharing rows, cols, T, d_lo, D, beta and precision (else R3D_EINVAL).
+ * hist: HOST array of nbands DEVICE pointers, fp16 [P][T] as for
+ * r3d_min_divergence. argmax: device int32 [P] (d_lo when the objective is
+ * -inf everywhere); value: device float [P] or NULL, the objective there
+ * (natural log, -inf when some band's correlation vanishes everywhere).
+ * Count errors are recorded in the first band's error word. */
+r3d_status r3d_min_divergence_msl(r3d_ctx *const *bands, int32_t nbands,
+                                  const uint16_t *const *hist, int32_t *argmax, float *value,
+                                  void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Pixel-dependent IRFs (Sec. II-A: the method applies when the shape of the
+ * IRF depends on the pixel).
+ * ------------------------------------------------------------------------- */
+
+/* One frame of Algorithm 1 as r3d_step_csr / r3d_step_hist, every pixel with
+ * its own IRF: the cost, the candidate bound and the background /
+ * reflectivity estimate use the pixel's taps. Exactly one input form:
+ * row_ptr + toa (CSR photon lists, as r3d_step_csr; hist NULL) or hist
+ * (device fp16 [P][T], any T; row_ptr and toa NULL). irf_pix: device double
+ * [P][W] (the context's W), row p the IRF of pixel p, non-negative with a
+ * positive tap, used verbatim; c_pix: device int32 [P], the tap of each
+ * pixel's IRF maximum (its depth reference, Sec. II-D), or NULL for the
+ * context's c. irf^beta is taken per pixel exactly as the context's IRF, so
+ * equal rows give the results of r3d_step_csr / r3d_step_hist. Evaluated in
+ * fp32 (one wavefront per pixel) whatever the context's precision. An
+ * invalid row or peak tap sets R3D_EINVAL in the device error word and
+ * leaves that pixel's outputs unwritten. Asynchronous. */
+r3d_status r3d_step_pirf(r3d_ctx *ctx, const int32_t *row_ptr, const int16_t *toa,
+                         const uint16_t *hist, const double *irf_pix, const int32_t *c_pix,
+                         const float *pi_in, const uint8_t *faulty, const r3d_state *prev,
+                         const r3d_state *next, const r3d_out *out, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batched sequences in one persistent launch.

@@ -12,23 +12,36 @@ namespace r3d {
 
 // a2: h = irf^beta (Sec. II-B), also split into fp16 high and scaled low
 // parts for the matrix-core contraction: h ~ hi + lo / 2048.
+// irf^beta of one tap (the shared IRF and the per-pixel ones alike)
+__device__ __forceinline__ double irf_pow(double x, double beta) { return x > 0.0 ? pow(x, beta) : 0.0; }
+
 __global__ void k_prepare_irf(const double* __restrict__ irf, int W, double beta,
                               float* __restrict__ h, float* __restrict__ irf32,
-                              _Float16* __restrict__ hi, _Float16* __restrict__ lo) {
+                              _Float16* __restrict__ hi, _Float16* __restrict__ lo,
+                              double* __restrict__ hmax) {
+  __shared__ double mx[256];
+  double m = 0.0;
   for (int j = threadIdx.x; j < W; j += blockDim.x) {
     const double x = irf[j];
-    const double hv = x > 0.0 ? pow(x, beta) : 0.0;
+    const double hv = irf_pow(x, beta);
     h[j] = (float)hv;
     irf32[j] = (float)x;
     const _Float16 a = (_Float16)hv;
     hi[j] = a;
     lo[j] = (_Float16)((hv - (double)a) * 2048.0);
+    m = fmax(m, hv);
+  }
+  mx[threadIdx.x] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)blockDim.x; ++i) m = fmax(m, mx[i]);
+    *hmax = m;
   }
 }
 
 hipError_t launch_prepare_irf(const double* irf_dev, int W, double beta, float* h, float* irf,
-                              _Float16* hi, _Float16* lo, hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare_irf, dim3(1), dim3(256), 0, s, irf_dev, W, beta, h, irf, hi, lo);
+                              _Float16* hi, _Float16* lo, double* hmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare_irf, dim3(1), dim3(256), 0, s, irf_dev, W, beta, h, irf, hi, lo, hmax);
   return hipGetLastError();
 }
 
@@ -117,7 +130,7 @@ __device__ __forceinline__ float load_hist_row(const DevModel& M, const uint16_t
   float ks = 0.f;
   for (int t = lane; t < M.T; t += 64) {
     const float x = half_bits_to_float(row[t]);
-    const bool ok = x >= 0.f && x <= kMaxFp16Count && x == truncf(x);
+    const bool ok = fp16_count_ok(row[t]);
     if (!ok) bad |= kErrOverflow;
     const float xc = ok ? x : 0.f;
     hist[t] = (unsigned)xc;
@@ -185,6 +198,67 @@ __global__ void __launch_bounds__(256) k_step_plain(DevModel M, StepIO io) {
   const int p = blockIdx.x * nw + wave;
   if (p >= M.P) return;
   pixel_step<kHist>(M, io, p, lane, hist, sh_h, sh_irf);
+}
+
+// One wavefront per pixel with the pixel's own IRF (Sec. II-A: the method
+// applies when the IRF shape depends on the pixel): the wavefront raises the
+// pixel's taps to beta exactly as the shared IRF is prepared (double pow,
+// rounded to fp32), bounds its largest power for the candidate range, and
+// runs the per-pixel step with the pixel's peak tap. A negative, non-finite
+// or all-zero row, or a peak tap outside [0, W), sets kErrIrf.
+template <bool kHist>
+__global__ void __launch_bounds__(256) k_step_pirf(DevModel M, StepIO io, const double* __restrict__ irf_pix,
+                                                   const int32_t* __restrict__ c_pix) {
+  extern __shared__ __align__(16) float smem_f[];
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tw = (2 * M.W + 3) & ~3;
+  float* sh_h = smem_f + wave * tw;
+  float* sh_irf = sh_h + M.W;
+  unsigned* hist = reinterpret_cast<unsigned*>(smem_f + nw * tw) + (size_t)wave * pixel_lds_words(M.T);
+  const int p = blockIdx.x * nw + wave;
+  if (p >= M.P) return;
+  const double* row = irf_pix + (size_t)p * M.W;
+  double hm = 0.0, tot = 0.0;
+  bool bad = false;
+  for (int j = lane; j < M.W; j += 64) {
+    const double x = row[j];
+    bad |= !(x >= 0.0) || !(x < 1e300);
+    const double hv = irf_pow(x, (double)M.beta_d);
+    sh_h[j] = (float)hv;
+    sh_irf[j] = (float)x;
+    hm = fmax(hm, hv);
+    tot += x;
+  }
+#pragma unroll
+  for (int m = 1; m <= 32; m <<= 1) {
+    hm = fmax(hm, __shfl_xor(hm, m));
+    tot += __shfl_xor(tot, m);
+  }
+  const int c = c_pix ? c_pix[p] : M.c;
+  bad |= !(tot > 0.0) || c < 0 || c >= M.W;
+  if (__any(bad)) {
+    if (lane == 0) atomicOr(M.err, kErrIrf);
+    return;
+  }
+  DevModel Mp = M;
+  Mp.c = c;
+  Mp.hmax = (float)(hm * (1.0 + 1e-6));
+  wave_fence();
+  pixel_step<kHist>(Mp, io, p, lane, hist, sh_h, sh_irf);
+}
+
+hipError_t launch_step_pirf(const DevModel& M, const StepIO& io, bool from_hist,
+                            const double* irf_pix, const int32_t* c_pix, hipStream_t s) {
+  const size_t tw = (size_t)((2 * M.W + 3) & ~3) * 4;
+  const int nw = waves_for(tw + (size_t)pixel_lds_words(M.T) * 4, 0);
+  if (nw == 0) return hipErrorInvalidValue;
+  const dim3 grid((M.P + nw - 1) / nw);
+  const size_t lds = nw * (tw + (size_t)pixel_lds_words(M.T) * 4);
+  if (from_hist)
+    hipLaunchKernelGGL(k_step_pirf<true>, grid, dim3(64 * nw), lds, s, M, io, irf_pix, c_pix);
+  else
+    hipLaunchKernelGGL(k_step_pirf<false>, grid, dim3(64 * nw), lds, s, M, io, irf_pix, c_pix);
+  return hipGetLastError();
 }
 
 static size_t step_plain_fixed(const DevModel& M) { return (size_t)((2 * M.W + 3) & ~3) * 4; }

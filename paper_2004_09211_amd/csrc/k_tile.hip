@@ -868,11 +868,19 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
       // count validation by the packed maximum of the raw fp16 bits
       float Kv = 0.f;
       ushort2 vmax = {0, 0};
+      unsigned vfrac = 0u;
       auto account = [&](half8 v) __attribute__((always_inline)) {
         const ushort8 u = __builtin_bit_cast(ushort8, v);
         const ushort2 m01 = __builtin_elementwise_max(ushort2{u[0], u[1]}, ushort2{u[2], u[3]});
         const ushort2 m23 = __builtin_elementwise_max(ushort2{u[4], u[5]}, ushort2{u[6], u[7]});
         vmax = __builtin_elementwise_max(vmax, __builtin_elementwise_max(m01, m23));
+        // non-integral counts: the fractional parts' bits, paired into 32-bit
+        // words and or-ed (16-bit or chains cost a spill at this register
+        // budget)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          vfrac |= __builtin_bit_cast(unsigned, half2{(_Float16)__builtin_amdgcn_fracth(v[2 * s]),
+                                                      (_Float16)__builtin_amdgcn_fracth(v[2 * s + 1])});
         const half2 one2 = {(_Float16)1.f, (_Float16)1.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) Kv = __builtin_amdgcn_fdot2(half2{v[2 * s], v[2 * s + 1]}, one2, Kv, false);
@@ -1001,8 +1009,8 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
           me = me + G.chunk < G.npairs ? me + G.chunk : G.npairs;
         }
       }
-      // > 2048 or negative
-      const unsigned bad = (vmax[0] > 0x6800u || vmax[1] > 0x6800u) ? kErrOverflow : 0u;
+      // above 2048, negative (sign bit set) or not an integer
+      const unsigned bad = (vmax[0] > 0x6800u || vmax[1] > 0x6800u || vfrac != 0) ? kErrOverflow : 0u;
       if (bad) atomicOr(M.err, bad);
       if (!flushed) flush(c);
       first = false;
@@ -1153,6 +1161,115 @@ __global__ void __launch_bounds__(256) k_tile_cost(DevModel M, TileGeom G, const
   }
 }
 
+// ============================ minimum divergence ============================
+// Minimum beta-divergence depth estimates, with no prior. The single-band
+// estimate maximises the cost ell(d) (Sec. II-B, last paragraph); the
+// multispectral one maximises sum_l log(c_l(d) / K_l), c_l the band's
+// correlation with its own irf^beta and K_l its photon count (Appendix,
+// eq. div_MSL), bands without photons left out. One wavefront per 4x4 pixel
+// block: a first sweep counts each band's photons (and validates the counts),
+// then every pair's exact cost (split fp16 on the matrix cores, or fp32) is
+// reduced to a running argmax per lane (the lowest depth among equal
+// values), merged over the pixel's four lanes.
+template <int kEng, int NBP, bool kMsl>
+__global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int l = 0; l < A.nb; ++l) tile_prologue<kEng, NBP>(A.M[l], A.G[l], smem + l * A.lds_band);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i16 = lane & 15, g = lane >> 4;
+  const DevModel& M0 = A.M[0];
+  const TileGeom& G0 = A.G[0];
+  const int idx = blockIdx.x * 4 + wave;
+  if (idx >= G0.nblk) return;
+  _Float16* ring_lds = reinterpret_cast<_Float16*>(smem + A.nb * A.lds_band) + wave * 16 * kRingT;
+
+  // photon count of each band (every block once) and count validation:
+  // integers in [0, 2048]
+  float Kb[kMaxBands];
+  unsigned mask = 0u;
+  unsigned bad = 0u;
+  for (int l = 0; l < A.nb; ++l) {
+    const LanePix L = lane_pixel(A.M[l], A.G[l], A.hist[l], nullptr, idx, i16, g);
+    float ks = 0.f;
+    for (int kb = 0; kb < A.G[l].nkb; ++kb) {
+      const half8 v = load_block(A.M[l], L, g, kb);
+      const ushort8 u = __builtin_bit_cast(ushort8, v);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        if (!fp16_count_ok(u[s])) bad |= kErrOverflow;
+        ks += (float)v[s];
+      }
+    }
+    Kb[l] = group_sum<16, 32>(ks);
+    mask |= (Kb[l] > 0.f ? 1u : 0u) << l;
+  }
+  if (bad) atomicOr(M0.err, bad);
+
+  const LanePix L0 = lane_pixel(M0, G0, A.hist[0], nullptr, idx, i16, g);
+  const int dhi = M0.d_lo + M0.D - 1;
+  float best = -INFINITY;
+  int bidx = 0x7fffffff;
+  for (int m = 0; m < G0.npairs; ++m) {
+    floatx4 J0 = {0.f, 0.f, 0.f, 0.f}, J1 = J0;
+    for (int l = 0; l < A.nb; ++l) {
+      const DevModel& Ml = A.M[l];
+      const TileGeom& Gl = A.G[l];
+      const LanePix L = lane_pixel(Ml, Gl, A.hist[l], nullptr, idx, i16, g);
+      half8 blk[NBP];
+#pragma unroll
+      for (int b = 0; b < NBP; ++b) blk[b] = load_block(Ml, L, g, Gl.kbA0 + m + b);
+      if constexpr (kEng == kEngValu) {
+        wave_sync();
+#pragma unroll
+        for (int b = 0; b < NBP; ++b) ring_store(ring_lds, i16, g, Gl.kbA0 + m + b, blk[b]);
+        wave_sync();
+      }
+      const half8* sA = reinterpret_cast<const half8*>(smem + l * A.lds_band + Gl.lda_band);
+      floatx4 c0, c1;
+      pair_cost<kEng, NBP>(Ml, sA, ring_lds, lane, m, blk, c0, c1);
+      if constexpr (kMsl) {
+        const bool use = (mask >> l) & 1u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          J0[q] += !use ? 0.f : (c0[q] > 0.f ? fast_log2(c0[q]) : -INFINITY);
+          J1[q] += !use ? 0.f : (c1[q] > 0.f ? fast_log2(c1[q]) : -INFINITY);
+        }
+      } else {
+        J0 = c0;
+        J1 = c1;
+      }
+    }
+#pragma unroll
+    for (int tau = 0; tau < 2; ++tau)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int d = M0.d_lo + 32 * m + 16 * tau + 4 * g + q;
+        const float v = tau ? J1[q] : J0[q];
+        if (L0.valid && d <= dhi && (v > best || (bidx == 0x7fffffff && v == best))) {
+          best = v;
+          bidx = d - M0.d_lo;
+        }
+      }
+  }
+  group_argmax<16, 32>(best, bidx);
+  if (bidx == 0x7fffffff) bidx = 0;
+  if (L0.valid && g == 0) {
+    float val;
+    if constexpr (kMsl) {
+      // log2 of the raw cost is log2 c_l + 11 for the split engine (its
+      // high part is scaled by 2^11)
+      const float sh = kEng == kEngMfma16x2 ? 11.f : 0.f;
+      float off = 0.f;
+      for (int l = 0; l < A.nb; ++l)
+        if ((mask >> l) & 1u) off += sh + fast_log2(Kb[l]);
+      val = best == -INFINITY ? -INFINITY : (best - off) * kLn2;
+    } else {
+      val = best * M0.scale2 * (kEng == kEngMfma16x2 ? (1.0f / 2048.0f) : 1.0f) * kLn2;
+    }
+    A.argmax[L0.p] = M0.d_lo + bidx;
+    if (A.value) A.value[L0.p] = val;
+  }
+}
+
 static int floor_div(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
 bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
@@ -1257,6 +1374,63 @@ hipError_t launch_cost_tile(const DevModel& M0, int engine, const uint16_t* hist
     case kEngValu: return launch_cost_eng<kEngValu>(M, G, hist, ell, s);
     case kEngMfma16: return launch_cost_eng<kEngMfma16>(M, G, hist, ell, s);
     case kEngMfma16x2: return launch_cost_eng<kEngMfma16x2>(M, G, hist, ell, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int kEng, bool kMsl>
+static hipError_t launch_mindiv_eng(const MindivArgs& A, int nbp, size_t lds, hipStream_t s) {
+  const dim3 grid((A.G[0].nblk + 3) / 4), block(256);
+  switch (nbp) {
+#define R3D_MD_CASE(N)                                                                  \
+  case N:                                                                               \
+    if (lds > 65536)                                                                    \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mindiv<kEng, N, kMsl>), \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
+    hipLaunchKernelGGL((k_mindiv<kEng, N, kMsl>), grid, block, lds, s, A);             \
+    break;
+    R3D_MD_CASE(2)
+    R3D_MD_CASE(3)
+    R3D_MD_CASE(4)
+    R3D_MD_CASE(5)
+#undef R3D_MD_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mindiv(const DevModel* M, const uint16_t* const* hist, int nb, int engine,
+                         bool msl, int32_t* argmax, float* value, hipStream_t s) {
+  if (nb < 1 || nb > kMaxBands || (!msl && nb != 1)) return hipErrorInvalidValue;
+  MindivArgs A{};
+  A.nb = nb;
+  A.argmax = argmax;
+  A.value = value;
+  int nbp = 2;
+  for (int l = 0; l < nb; ++l) {
+    A.M[l] = M[l];
+    A.hist[l] = hist[l];
+    if (!tile_geometry(M[l], engine, A.G[l])) return hipErrorInvalidValue;
+    nbp = A.G[l].nbp > nbp ? A.G[l].nbp : nbp;
+  }
+  // every band's A operands are built for the widest band (extra blocks
+  // carry zero taps); each band region holds its staging and A operands
+  int band = 0;
+  for (int l = 0; l < nb; ++l) {
+    A.G[l].nbp = nbp;
+    A.G[l].lda_band = ((12 * M[l].W + 15) / 16) * 16;
+    const int need = A.G[l].lda_band + (engine == kEngValu ? 0 : 2 * 2 * nbp * 64 * 16);
+    band = need > band ? need : band;
+  }
+  for (int l = 0; l < nb; ++l) A.G[l].lds_a = A.G[l].lda_band;
+  A.lds_band = band;
+  const size_t lds = (size_t)nb * band + (engine == kEngValu ? 4 * 16 * kRingT * 2 : 0);
+  const int lds_max = M[0].lds_max > 0 ? M[0].lds_max : 65536;
+  if (lds > (size_t)lds_max) return hipErrorInvalidValue;
+  switch (engine) {
+    case kEngValu: return msl ? launch_mindiv_eng<kEngValu, true>(A, nbp, lds, s) : launch_mindiv_eng<kEngValu, false>(A, nbp, lds, s);
+    case kEngMfma16: return msl ? launch_mindiv_eng<kEngMfma16, true>(A, nbp, lds, s) : launch_mindiv_eng<kEngMfma16, false>(A, nbp, lds, s);
+    case kEngMfma16x2: return msl ? launch_mindiv_eng<kEngMfma16x2, true>(A, nbp, lds, s) : launch_mindiv_eng<kEngMfma16x2, false>(A, nbp, lds, s);
   }
   return hipErrorInvalidValue;
 }

@@ -35,6 +35,8 @@ r3d_status check_params(const r3d_params* p) {
   if ((int64_t)p->rows * p->cols > (int64_t)1 << 30) return R3D_EUNSUPPORTED;
   if (p->T < 1 || p->T > 32767) return R3D_EINVAL;
   if (p->D < 1 || p->D > 32768) return R3D_EINVAL;
+  // grid depths stay exact in fp32 and d_lo + D - 1 cannot overflow
+  if (p->d_lo < -(1 << 20) || p->d_lo > (1 << 20)) return R3D_EINVAL;
   if (p->W < 1 || p->W > r3d::kMaxW) return R3D_EINVAL;
   if (p->c < 0 || p->c >= p->W) return R3D_EINVAL;
   if (!p->irf) return R3D_EINVAL;
@@ -149,17 +151,21 @@ r3d_status r3d_create(const r3d_params* params, r3d_ctx** out) {
       hipMalloc(&c->d_irf, W * sizeof(float)) != hipSuccess ||
       hipMalloc(&c->d_h16, 2 * W * sizeof(_Float16)) != hipSuccess ||
       hipMalloc(&c->d_err, sizeof(unsigned)) != hipSuccess ||
-      hipMalloc(&d_irf64, W * sizeof(double)) != hipSuccess) {
+      hipMalloc(&d_irf64, (W + 1) * sizeof(double)) != hipSuccess) {
     if (d_irf64) (void)hipFree(d_irf64);
     free_ctx(c);
     return R3D_ENOMEM;
   }
+  // the largest irf^beta, taken on the device with the same power function
+  // as the per-pixel IRF step (d_irf64[W])
+  double hmax = 0.0;
   hipError_t e = hipMemcpy(d_irf64, c->irf.data(), W * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(unsigned));
   if (e == hipSuccess)
     e = r3d::launch_prepare_irf(d_irf64, W, params->beta, c->d_h, c->d_irf, c->d_h16,
-                                c->d_h16 + W, nullptr);
+                                c->d_h16 + W, d_irf64 + W, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&hmax, d_irf64 + W, sizeof(double), hipMemcpyDeviceToHost);
   (void)hipFree(d_irf64);
   if (e != hipSuccess) {
     free_ctx(c);
@@ -176,9 +182,8 @@ r3d_status r3d_create(const r3d_params* params, r3d_ctx** out) {
   m.W = W;
   m.c = params->c;
   m.beta = (float)params->beta;
+  m.beta_d = params->beta;
   m.scale2 = (float)((params->beta + 1.0) / params->beta * 1.4426950408889634);
-  double hmax = 0.0;
-  for (int j = 0; j < W; ++j) hmax = std::fmax(hmax, std::pow(c->irf[j], params->beta));
   m.hmax = (float)(hmax * (1.0 + 1e-6));
   m.m_flat = (float)(0.5 * (params->d_min + params->d_max));
   const double span = params->d_max - params->d_min;
@@ -193,6 +198,13 @@ r3d_status r3d_create(const r3d_params* params, r3d_ctx** out) {
   m.h16hi = c->d_h16;
   m.h16lo = c->d_h16 + W;
   m.err = c->d_err;
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) !=
+      hipSuccess) {
+    free_ctx(c);
+    return R3D_EHIP;
+  }
+  m.lds_max = lds_max;
   if (!r3d::plain_supported(m)) {
     free_ctx(c);
     return R3D_EUNSUPPORTED;
@@ -290,6 +302,52 @@ r3d_status r3d_run_hist(r3d_ctx* ctx, const uint16_t* const* hist, int32_t nfram
   return R3D_OK;
 }
 
+r3d_status r3d_step_pirf(r3d_ctx* ctx, const int32_t* row_ptr, const int16_t* toa,
+                         const uint16_t* hist, const double* irf_pix, const int32_t* c_pix,
+                         const float* pi_in, const uint8_t* faulty, const r3d_state* prev,
+                         const r3d_state* next, const r3d_out* out, void* stream) {
+  if (!ctx || !irf_pix) return R3D_EINVAL;
+  if ((row_ptr != nullptr) == (hist != nullptr)) return R3D_EINVAL;  // exactly one input form
+  if (check_state(prev) != R3D_OK || check_state(next) != R3D_OK) return R3D_EINVAL;
+  if (same_buffer(prev, next)) return R3D_EINVAL;
+  r3d::StepIO io = make_io(pi_in, faulty, prev, next, out);
+  io.row_ptr = row_ptr;
+  io.toa = toa;
+  io.hist = hist;
+  return hip_status(r3d::launch_step_pirf(ctx->dm, io, hist != nullptr, irf_pix, c_pix,
+                                          (hipStream_t)stream));
+}
+
+r3d_status r3d_min_divergence(r3d_ctx* ctx, const uint16_t* hist, int32_t* argmax, float* value,
+                              void* stream) {
+  if (!ctx || !hist || !argmax) return R3D_EINVAL;
+  if ((uintptr_t)hist & 15u) return R3D_EUNSUPPORTED;
+  const uint16_t* h[1] = {hist};
+  return hip_status(r3d::launch_mindiv(&ctx->dm, h, 1, ctx->prm.precision, false, argmax, value,
+                                       (hipStream_t)stream));
+}
+
+r3d_status r3d_min_divergence_msl(r3d_ctx* const* bands, int32_t nbands,
+                                  const uint16_t* const* hist, int32_t* argmax, float* value,
+                                  void* stream) {
+  if (!bands || !hist || !argmax || nbands < 1) return R3D_EINVAL;
+  if (nbands > r3d::kMaxBands) return R3D_EUNSUPPORTED;
+  r3d::DevModel M[r3d::kMaxBands];
+  const r3d_params& p0 = bands[0] ? bands[0]->prm : r3d_params{};
+  for (int l = 0; l < nbands; ++l) {
+    if (!bands[l] || !hist[l]) return R3D_EINVAL;
+    const r3d_params& p = bands[l]->prm;
+    if (p.rows != p0.rows || p.cols != p0.cols || p.T != p0.T || p.d_lo != p0.d_lo ||
+        p.D != p0.D || p.beta != p0.beta || p.precision != p0.precision)
+      return R3D_EINVAL;
+    if ((uintptr_t)hist[l] & 15u) return R3D_EUNSUPPORTED;
+    M[l] = bands[l]->dm;
+    M[l].err = bands[0]->d_err;  // one error word for the call
+  }
+  return hip_status(r3d::launch_mindiv(M, hist, nbands, p0.precision, true, argmax, value,
+                                       (hipStream_t)stream));
+}
+
 }  // extern "C"
 
 struct r3d_batch {
@@ -321,6 +379,7 @@ void free_batch(r3d_batch* b) {
 }
 
 r3d_status device_bits(unsigned bits) {
+  if (bits & r3d::kErrIrf) return R3D_EINVAL;
   if (bits & r3d::kErrTimeout) return R3D_ETIMEDOUT;
   if (bits & r3d::kErrRange) return R3D_ERANGE;
   if (bits & r3d::kErrOverflow) return R3D_EOVERFLOW;

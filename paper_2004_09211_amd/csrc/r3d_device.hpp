@@ -20,6 +20,13 @@ __device__ __forceinline__ float half_bits_to_float(uint16_t b) {
   return (float)h;
 }
 
+// A histogram count as the paths take it: an fp16 integer in [0, 2048] with
+// a clear sign bit (so -0 is rejected like a negative count).
+__device__ __forceinline__ bool fp16_count_ok(uint16_t b) {
+  const float x = half_bits_to_float(b);
+  return !(b & 0x8000u) && x <= kMaxFp16Count && x == truncf(x);
+}
+
 template <int kLo, int kHi>
 __device__ __forceinline__ float group_sum(float x) {
 #pragma unroll

@@ -15,13 +15,14 @@ constexpr int kMaxW = 256;
 constexpr float kMaxFp16Count = 2048.0f;  // largest count fp16 holds exactly with all below
 
 // error bits of the device error word
-enum : unsigned { kErrRange = 1u, kErrOverflow = 2u, kErrTimeout = 4u };
+enum : unsigned { kErrRange = 1u, kErrOverflow = 2u, kErrTimeout = 4u, kErrIrf = 8u };
 
 // Model in the form the kernels use; passed by value as a kernel argument.
 // Log-quantities are in base 2 (the hardware exp/log are base 2).
 struct DevModel {
   int rows, cols, P, T, d_lo, D, W, c;
   float beta;        // beta-divergence parameter
+  double beta_d;     // the same in double (IRF powers are taken in double)
   float scale2;      // (beta+1)/beta * log2(e): cost in log2 units
   float hmax;        // an upper bound of max_j irf^beta[j] (for the culling bound)
   float m_flat;      // (d_min+d_max)/2
@@ -34,6 +35,7 @@ struct DevModel {
   const _Float16* h16hi;  // fp16(irf^beta) [W]
   const _Float16* h16lo;  // fp16((irf^beta - hi) * 2048) [W]
   unsigned* err;     // device error word
+  int lds_max;       // bytes of LDS a workgroup may use on this device
 };
 
 // Per-step pointers (device memory, caller-owned).
@@ -52,7 +54,7 @@ struct StepIO {
 
 // launchers (one translation unit each)
 hipError_t launch_prepare_irf(const double* irf_dev, int W, double beta, float* h, float* irf,
-                              _Float16* hi, _Float16* lo, hipStream_t s);
+                              _Float16* hi, _Float16* lo, double* hmax, hipStream_t s);
 hipError_t launch_state_init(const DevModel& m, float* sm, float* sv, float* spi, float* sb,
                              hipStream_t s);
 hipError_t launch_histogram(const DevModel& m, const int32_t* row_ptr, const int16_t* toa,
@@ -60,6 +62,10 @@ hipError_t launch_histogram(const DevModel& m, const int32_t* row_ptr, const int
 hipError_t launch_cost_plain(const DevModel& m, const uint16_t* hist, int npix, float* ell,
                              hipStream_t s);
 hipError_t launch_step_plain(const DevModel& m, const StepIO& io, bool from_hist, hipStream_t s);
+// the per-pixel step with every pixel's own IRF: irf_pix double [P][W],
+// c_pix int32 [P] or null (the model's c)
+hipError_t launch_step_pirf(const DevModel& m, const StepIO& io, bool from_hist,
+                            const double* irf_pix, const int32_t* c_pix, hipStream_t s);
 bool plain_supported(const DevModel& m);
 
 }  // namespace r3d

@@ -240,7 +240,7 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
           const int t = 2 * w + h;
           if (t < M.T) {
             const float x = half_bits_to_float(row[t]);
-            const bool ok = x >= 0.f && x <= kMaxFp16Count && x == truncf(x);
+            const bool ok = fp16_count_ok(row[t]);
             if (!ok) bad |= kErrOverflow;
             const unsigned n = ok ? (unsigned)x : 0u;
             packed |= n << (16 * h);

@@ -35,7 +35,23 @@ struct TileGeom {
   int chunk;       // pairs per chunk of a shared block
   int nchunks;     // ceil(npairs / chunk) <= kMaxChunks
   int waves;       // wavefronts per workgroup of the step
+  int lda_band;    // minimum-divergence kernels: offset of a band's A operands in its region
 };
+
+// Minimum-divergence estimates: up to kMaxBands bands sharing the frame, T,
+// the depth grid and beta, each with its own IRF (its own model).
+constexpr int kMaxBands = 4;
+struct MindivArgs {
+  DevModel M[kMaxBands];
+  TileGeom G[kMaxBands];
+  const uint16_t* hist[kMaxBands];
+  int nb;        // bands
+  int lds_band;  // LDS bytes per band (IRF staging and A operands)
+  int32_t* argmax;
+  float* value;
+};
+hipError_t launch_mindiv(const DevModel* M, const uint16_t* const* hist, int nb, int engine,
+                         bool msl, int32_t* argmax, float* value, hipStream_t s);
 
 bool tile_geometry(const DevModel& M, int engine, TileGeom& G);
 bool tile_supported(const DevModel& M, int engine);

@@ -83,6 +83,12 @@ SIGNATURES = {
                                      c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
     "r3d_filter_backward": (c_int32, [c_void_p, POINTER(CFrames), c_int32, c_void_p, c_void_p,
                                       c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),
+    "r3d_min_divergence": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "r3d_min_divergence_msl": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_void_p,
+                                         c_void_p, c_void_p]),
+    "r3d_step_pirf": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_void_p, POINTER(CState), POINTER(CState),
+                                POINTER(COut), c_void_p]),
     "r3d_status_string": (c_char_p, [c_int32]),
 }
 
@@ -267,6 +273,32 @@ class Context:
     def last_device_status(self, stream=None) -> int:
         return int(_lib.r3d_last_device_status(self._h, _stream(stream)))
 
+    def min_divergence(self, hist: torch.Tensor, argmax=None, value=None, stream=None):
+        """Minimum beta-divergence depth (no prior) of each pixel of the fp16
+        histograms [P, T]; returns (argmax int32 [P], value float [P])."""
+        if argmax is None:
+            argmax = torch.empty(self.P, dtype=torch.int32, device=hist.device)
+        if value is None:
+            value = torch.empty(self.P, dtype=torch.float32, device=hist.device)
+        _check(_lib.r3d_min_divergence(self._h, _ptr(hist, torch.float16), _ptr(argmax, torch.int32),
+                                       _ptr(value, torch.float32), _stream(stream)),
+               "r3d_min_divergence")
+        return argmax, value
+
+    def step_pirf(self, frame, irf_pix, prev: State, nxt: State, out: Outputs, c_pix=None,
+                  pi_in=None, faulty=None, stream=None):
+        """One frame with a per-pixel IRF: ``frame`` is an fp16 [P, T] histogram
+        tensor or a (row_ptr, toa) photon list; ``irf_pix`` float64 [P, W]."""
+        if isinstance(frame, torch.Tensor):
+            rp, toa, hist = None, None, _ptr(frame, torch.float16)
+        else:
+            rp, toa, hist = _ptr(frame[0], torch.int32), _ptr(frame[1], torch.int16), None
+        cp, cn, co = prev.c(), nxt.c(), out.c()
+        _check(_lib.r3d_step_pirf(self._h, rp, toa, hist, _ptr(irf_pix, torch.float64),
+                                  _ptr(c_pix, torch.int32), _ptr(pi_in, torch.float32),
+                                  _ptr(faulty, torch.uint8), byref(cp), byref(cn), byref(co),
+                                  _stream(stream)), "r3d_step_pirf")
+
     def grad_workspace_size(self, nframes: int, ckpt_every: int) -> int:
         n = ctypes.c_size_t()
         _check(_lib.r3d_grad_workspace_size(self._h, int(nframes), int(ckpt_every), byref(n)),
@@ -289,6 +321,26 @@ class Context:
                                         _ptr(workspace, torch.uint8), workspace.numel(),
                                         _ptr(grad, torch.float64), _stream(stream)),
                "r3d_filter_backward")
+
+
+def min_divergence_msl(bands, hists, argmax=None, value=None, stream=None):
+    """Minimum multispectral beta-divergence depth: ``bands`` one Context per
+    band (its own IRF), ``hists`` one fp16 [P, T] tensor per band; returns
+    (argmax int32 [P], value float [P])."""
+    n = len(bands)
+    P = bands[0].P
+    dev = hists[0].device
+    if argmax is None:
+        argmax = torch.empty(P, dtype=torch.int32, device=dev)
+    if value is None:
+        value = torch.empty(P, dtype=torch.float32, device=dev)
+    bp = (c_void_p * n)(*[b._h for b in bands])
+    hp = (c_void_p * n)(*[_ptr(h, torch.float16) for h in hists])
+    _check(_lib.r3d_min_divergence_msl(ctypes.cast(bp, POINTER(c_void_p)), n,
+                                       ctypes.cast(hp, POINTER(c_void_p)), _ptr(argmax, torch.int32),
+                                       _ptr(value, torch.float32), _stream(stream)),
+           "r3d_min_divergence_msl")
+    return argmax, value
 
 
 class Frames:

@@ -128,7 +128,7 @@ def test_step_tile_edge_cases(lib, prec, case):
 def test_tile_count_validation(lib):
     wl = hist_workload(rows=4, cols=4, frames=1, T=256)
     h = wl.hist[0].to(DEV).clone()
-    for bad in (2050.0, -1.0):
+    for bad in (2050.0, -1.0, 1.5, -0.0):
         h2 = h.clone()
         h2[5, 17] = bad
         for prec in ENGINES:
@@ -186,9 +186,10 @@ def _bits(t: torch.Tensor) -> torch.Tensor:
 @pytest.mark.parametrize("case", ["crop", "faulty_pi", "one_frame"])
 @pytest.mark.parametrize("prec", ENGINES)
 def test_run_hist_equals_per_frame_steps(lib, prec, case):
-    """The sequence call, which computes the cost bounds of frame n+1 in the
-    launch that resolves frame n, gives bit-identical outputs and states to
-    one step per frame (13x18 crop: ragged 4x4 blocks)."""
+    """The sequence call (one tile-step launch per frame on the caller's
+    stream, states ping-ponged between its two buffers, outputs written at
+    frame offsets) gives bit-identical outputs and states to one step call
+    per frame (13x18 crop: ragged 4x4 blocks)."""
     frames = 1 if case == "one_frame" else 4
     wl = hist_workload(rows=13, cols=18, frames=frames)
     P = wl.P
