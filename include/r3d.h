@@ -56,7 +56,8 @@ typedef enum {
     R3D_ENOMEM = -4,        /* device allocation failed                         */
     R3D_EHIP = -5,          /* a HIP runtime call failed                        */
     R3D_EUNSUPPORTED = -6,  /* size or option outside what the kernels support  */
-    R3D_ETIMEDOUT = -7      /* a batched item waited past its spin limit        */
+    R3D_ETIMEDOUT = -7,     /* a batched item waited past its spin limit        */
+    R3D_ETOOBIG = -8        /* tables beyond r3d_batch_run_noalloc's scratch    */
 } r3d_status;
 
 /* How the cost correlation (a3) is evaluated.
@@ -292,6 +293,25 @@ r3d_status r3d_batch_status(r3d_batch *batch, void *stream);
 
 /* Destroy a batch (synchronises the device first). NULL is ignored. */
 void r3d_batch_destroy(r3d_batch *batch);
+
+/* For callers that cannot allocate device memory (serving loops that must
+ * not call hipMalloc or hipFree): the batch of r3d_batch_create run once on
+ * the stream, without creating a batch object and without any allocation.
+ * The sequence descriptors, frame pointer table, work counter and done
+ * counters live in a static device array of 4 MiB per GPU (held until the
+ * process ends); tables larger than that (about 336 bytes per sequence, 16
+ * per frame and 4 per chunk of rows, in 256-byte aligned sections) return
+ * R3D_ETOOBIG before anything is enqueued. Arguments,
+ * checks and results are those of r3d_batch_create + r3d_batch_launch; the
+ * outputs are bit-identical. Device errors (R3D_ETIMEDOUT, R3D_ERANGE,
+ * R3D_EOVERFLOW) are recorded in seqs[0].ctx's error word: read them with
+ * r3d_last_device_status(seqs[0].ctx, stream). The call blocks until its
+ * tables are uploaded (it synchronises the stream once, before the launch),
+ * then returns with the batch running. Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other host threads, other streams)
+ * race and give undefined results. Not for use under stream capture. */
+r3d_status r3d_batch_run_noalloc(const r3d_sequence *seqs, int32_t nseq,
+                                 const r3d_batch_options *opt, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Differentiable filter.

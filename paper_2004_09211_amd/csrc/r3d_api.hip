@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "r3d_internal.hpp"
@@ -115,6 +116,42 @@ void free_ctx(r3d_ctx* c) {
 
 }  // namespace
 
+// Device tables of r3d_batch_run_noalloc (sequence descriptors, chunk prefix,
+// frame pointers, work counter, done counters): a fixed array in every GPU's
+// memory, held until the process ends. Host code uses the address that
+// hipGetSymbolAddress returns for the current device, never the array's name.
+constexpr size_t kBatchScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kBatchScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+// host staging of the tables; guarded by g_stage_mu until their upload ends
+std::mutex g_stage_mu;
+alignas(256) unsigned char g_stage[kBatchScratchBytes];
+
+// The scratch array's device address on the current device, resolved once
+// per device (with that device current).
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* r3d_status_string(r3d_status s) {
@@ -127,6 +164,7 @@ const char* r3d_status_string(r3d_status s) {
     case R3D_EHIP: return "HIP runtime error";
     case R3D_EUNSUPPORTED: return "unsupported size or option";
     case R3D_ETIMEDOUT: return "a batched work item waited past its spin limit";
+    case R3D_ETOOBIG: return "batch tables larger than the 4 MiB static scratch array";
   }
   return "unknown status";
 }
@@ -141,7 +179,8 @@ r3d_status r3d_create(const r3d_params* params, r3d_ctx** out) {
   c->prm = *params;
   c->irf.assign(params->irf, params->irf + params->W);
   c->prm.irf = nullptr;
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  void* scratch_dev = nullptr;  // resolves the device's scratch address once
+  if (hipGetDevice(&c->device) != hipSuccess || scratch_address(&scratch_dev) != hipSuccess) {
     free_ctx(c);
     return R3D_EHIP;
   }
@@ -386,22 +425,13 @@ r3d_status device_bits(unsigned bits) {
   return R3D_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq,
-                            const r3d_batch_options* opt, r3d_batch** out) {
-  if (!out) return R3D_EINVAL;
-  *out = nullptr;
+// First pass over a batch: argument checks and the length of its frame
+// pointer table.
+r3d_status batch_count(const r3d_sequence* seqs, int32_t nseq, const r3d_batch_options* opt,
+                       size_t& nptrs) {
   if (!seqs || nseq < 1) return R3D_EINVAL;
-  const uint32_t spin_limit = opt ? opt->spin_limit : 0u;
-  const int req_blocks = opt ? opt->blocks : 0;
-  if (req_blocks < 0) return R3D_EINVAL;
-  std::vector<r3d::SeqDesc> host(nseq);
-  std::vector<int> prefix(nseq + 1, 0);
-  std::vector<void*> ptrs;
-  int tmax = 1, fmax = 1;
+  if (opt && opt->blocks < 0) return R3D_EINVAL;
+  nptrs = 0;
   for (int s = 0; s < nseq; ++s) {
     const r3d_sequence& q = seqs[s];
     if (!q.ctx || q.nframes < 1 || !q.row_ptr || !q.toa || q.chunk_rows < 0) return R3D_EINVAL;
@@ -410,8 +440,26 @@ r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq,
     if (q.ctx->prm.precision != R3D_FP32) return R3D_EUNSUPPORTED;
     for (int n = 0; n < q.nframes; ++n)
       if (!q.row_ptr[n] || !q.toa[n]) return R3D_EINVAL;
+    nptrs += 2 * (size_t)q.nframes;
+  }
+  return R3D_OK;
+}
+
+// Second pass: the sequence descriptors, the chunk prefix [nseq + 1] and the
+// frame pointer table, written to host memory; d_ptrs is the device address
+// the table will have (the descriptors point into it). Fills the geometry
+// except its device pointers.
+r3d_status batch_fill(const r3d_sequence* seqs, int32_t nseq, const r3d_batch_options* opt,
+                      r3d::SeqDesc* desc, int* prefix, void** ptrs, void** d_ptrs,
+                      r3d::BatchGeom& G) {
+  size_t np = 0;
+  int tmax = 1, fmax = 1;
+  prefix[0] = 0;
+  for (int s = 0; s < nseq; ++s) {
+    const r3d_sequence& q = seqs[s];
     const r3d::DevModel& M = q.ctx->dm;
-    r3d::SeqDesc& d = host[s];
+    r3d::SeqDesc& d = desc[s];
+    d = r3d::SeqDesc{};
     d.M = M;
     d.nframes = q.nframes;
     d.chunk_rows = q.chunk_rows > 0 ? q.chunk_rows : (256 + M.cols - 1) / M.cols;
@@ -419,10 +467,10 @@ r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq,
     d.nchunks = (M.rows + d.chunk_rows - 1) / d.chunk_rows;
     d.done_off = prefix[s];
     prefix[s + 1] = prefix[s] + d.nchunks;
-    d.row_ptr = reinterpret_cast<const int32_t* const*>(ptrs.size());  // offset, fixed below
-    for (int n = 0; n < q.nframes; ++n) ptrs.push_back((void*)q.row_ptr[n]);
-    d.toa = reinterpret_cast<const int16_t* const*>(ptrs.size());
-    for (int n = 0; n < q.nframes; ++n) ptrs.push_back((void*)q.toa[n]);
+    d.row_ptr = reinterpret_cast<const int32_t* const*>(d_ptrs + np);
+    for (int n = 0; n < q.nframes; ++n) ptrs[np++] = (void*)q.row_ptr[n];
+    d.toa = reinterpret_cast<const int16_t* const*>(d_ptrs + np);
+    for (int n = 0; n < q.nframes; ++n) ptrs[np++] = (void*)q.toa[n];
     for (int i = 0; i < 2; ++i) {
       d.st_m[i] = q.state[i].m;
       d.st_v[i] = q.state[i].v;
@@ -440,7 +488,8 @@ r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq,
     tmax = std::max(tmax, M.T);
     fmax = std::max(fmax, q.nframes);
   }
-  r3d::BatchGeom G{};
+  const uint32_t spin_limit = opt ? opt->spin_limit : 0u;
+  G = r3d::BatchGeom{};
   G.nseq = nseq;
   G.chunks_total = prefix[nseq];
   G.hist_words = r3d::pixel_lds_words(tmax);
@@ -450,37 +499,65 @@ r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq,
   G.nitems = (unsigned)nitems;
   G.spin_limit = spin_limit ? spin_limit : (1u << 22);
   G.ndone = G.chunks_total;
+  return R3D_OK;
+}
 
+int batch_blocks(const r3d::BatchGeom& G, const r3d_batch_options* opt, hipError_t& e) {
+  const int req = opt ? opt->blocks : 0;
+  if (req > 0) return req;
+  int dev = 0, ncu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  return std::max(1, ncu) * r3d::batch_blocks_per_cu(G);
+}
+
+}  // namespace
+
+extern "C" {
+
+r3d_status r3d_batch_create(const r3d_sequence* seqs, int32_t nseq,
+                            const r3d_batch_options* opt, r3d_batch** out) {
+  if (!out) return R3D_EINVAL;
+  *out = nullptr;
+  size_t nptrs = 0;
+  r3d_status st = batch_count(seqs, nseq, opt, nptrs);
+  if (st != R3D_OK) return st;
+  std::vector<r3d::SeqDesc> host(nseq);
+  std::vector<int> prefix(nseq + 1, 0);
+  std::vector<void*> ptrs(nptrs);
   r3d_batch* b = new (std::nothrow) r3d_batch();
   if (!b) return R3D_ENOMEM;
+  if (hipMalloc(&b->d_ptrs, nptrs * sizeof(void*)) != hipSuccess) {
+    free_batch(b);
+    return R3D_ENOMEM;
+  }
+  r3d::BatchGeom G{};
+  st = batch_fill(seqs, nseq, opt, host.data(), prefix.data(), ptrs.data(), b->d_ptrs, G);
+  if (st != R3D_OK) {
+    free_batch(b);
+    return st;
+  }
   if (hipMalloc(&b->d_seqs, nseq * sizeof(r3d::SeqDesc)) != hipSuccess ||
       hipMalloc(&b->d_prefix, (nseq + 1) * sizeof(int)) != hipSuccess ||
-      hipMalloc(&b->d_ptrs, ptrs.size() * sizeof(void*)) != hipSuccess ||
       hipMalloc(&b->d_queue, sizeof(unsigned)) != hipSuccess ||
       hipMalloc(&b->d_done, G.ndone * sizeof(int)) != hipSuccess ||
       hipMalloc(&b->d_err, sizeof(unsigned)) != hipSuccess) {
     free_batch(b);
     return R3D_ENOMEM;
   }
-  for (auto& d : host) {  // turn pointer-array offsets into device addresses
-    d.row_ptr = reinterpret_cast<const int32_t* const*>(b->d_ptrs + (size_t)d.row_ptr);
-    d.toa = reinterpret_cast<const int16_t* const*>(b->d_ptrs + (size_t)d.toa);
-  }
   G.chunk_prefix = b->d_prefix;
   G.queue = b->d_queue;
   G.done = b->d_done;
   G.err = b->d_err;
-  int dev = 0, ncu = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  hipError_t e = hipSuccess;
+  const int blocks = batch_blocks(G, opt, e);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_seqs, host.data(), nseq * sizeof(r3d::SeqDesc), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_prefix, prefix.data(), (nseq + 1) * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpy(b->d_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice);
+    e = hipMemcpy(b->d_ptrs, ptrs.data(), nptrs * sizeof(void*), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(b->d_err, 0, sizeof(unsigned));
-  const int blocks = req_blocks > 0 ? req_blocks : std::max(1, ncu) * r3d::batch_blocks_per_cu(G);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
@@ -517,6 +594,45 @@ void r3d_batch_destroy(r3d_batch* b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   free_batch(b);
+}
+
+r3d_status r3d_batch_run_noalloc(const r3d_sequence* seqs, int32_t nseq,
+                                 const r3d_batch_options* opt, void* stream) {
+  size_t nptrs = 0;
+  r3d_status st = batch_count(seqs, nseq, opt, nptrs);
+  if (st != R3D_OK) return st;
+  // table sections in the scratch array, 256-byte aligned
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_prefix = up((size_t)nseq * sizeof(r3d::SeqDesc));
+  const size_t o_ptrs = up(o_prefix + (size_t)(nseq + 1) * sizeof(int));
+  const size_t o_queue = up(o_ptrs + nptrs * sizeof(void*));
+  const size_t o_done = o_queue + 256;
+  if (o_done > kBatchScratchBytes) return R3D_ETOOBIG;
+  void* addr = nullptr;
+  if (scratch_address(&addr) != hipSuccess) return R3D_EHIP;
+  unsigned char* base = static_cast<unsigned char*>(addr);
+  const hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  r3d::BatchGeom G{};
+  st = batch_fill(seqs, nseq, opt, reinterpret_cast<r3d::SeqDesc*>(g_stage),
+                  reinterpret_cast<int*>(g_stage + o_prefix),
+                  reinterpret_cast<void**>(g_stage + o_ptrs),
+                  reinterpret_cast<void**>(base + o_ptrs), G);
+  if (st != R3D_OK) return st;
+  if (o_done + (size_t)G.ndone * sizeof(int) > kBatchScratchBytes) return R3D_ETOOBIG;
+  G.chunk_prefix = reinterpret_cast<const int*>(base + o_prefix);
+  G.queue = reinterpret_cast<unsigned*>(base + o_queue);
+  G.done = reinterpret_cast<int*>(base + o_done);
+  G.err = seqs[0].ctx->d_err;
+  hipError_t e = hipSuccess;
+  const int blocks = batch_blocks(G, opt, e);
+  // the staging area serves the next call: its upload ends before the
+  // launch (the work counter and done counters are cleared by the launch)
+  if (e == hipSuccess) e = hipMemcpyAsync(base, g_stage, o_queue, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess)
+    e = r3d::launch_batch(reinterpret_cast<const r3d::SeqDesc*>(base), G, blocks, s);
+  return e == hipSuccess ? R3D_OK : R3D_EHIP;
 }
 
 }  // extern "C"

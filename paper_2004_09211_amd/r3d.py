@@ -22,7 +22,8 @@ R3D_FP32, R3D_FP16_MFMA, R3D_FP16X2_MFMA = 0, 1, 2
 PRECISIONS = {"fp32": R3D_FP32, "fp16": R3D_FP16_MFMA, "fp16x2": R3D_FP16X2_MFMA}
 
 STATUS = {0: "R3D_OK", -1: "R3D_EINVAL", -2: "R3D_ERANGE", -3: "R3D_EOVERFLOW",
-          -4: "R3D_ENOMEM", -5: "R3D_EHIP", -6: "R3D_EUNSUPPORTED", -7: "R3D_ETIMEDOUT"}
+          -4: "R3D_ENOMEM", -5: "R3D_EHIP", -6: "R3D_EUNSUPPORTED", -7: "R3D_ETIMEDOUT",
+          -8: "R3D_ETOOBIG"}
 
 STATUS_CODES = {v: k for k, v in STATUS.items()}
 
@@ -78,6 +79,8 @@ SIGNATURES = {
     "r3d_batch_launch": (c_int32, [c_void_p, c_void_p]),
     "r3d_batch_status": (c_int32, [c_void_p, c_void_p]),
     "r3d_batch_destroy": (None, [c_void_p]),
+    "r3d_batch_run_noalloc": (c_int32, [POINTER(CSequence), c_int32, POINTER(CBatchOptions),
+                                        c_void_p]),
     "r3d_grad_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, POINTER(ctypes.c_size_t)]),
     "r3d_filter_forward": (c_int32, [c_void_p, POINTER(CFrames), c_int32, POINTER(CState),
                                      c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
@@ -424,6 +427,43 @@ class Sequence:
         self.ctx.state_init(self.states[0], stream)
 
 
+def _c_sequences(seqs):
+    """The r3d_sequence array of a list of Sequence objects, and the host
+    pointer arrays it refers to (keep them alive during the call)."""
+    arr = (CSequence * len(seqs))()
+    keep = []
+    for i, q in enumerate(seqs):
+        n = len(q.frames)
+        rp = (c_void_p * n)(*[_ptr(f[0], torch.int32) for f in q.frames])
+        ta = (c_void_p * n)(*[_ptr(f[1], torch.int16) for f in q.frames])
+        keep += [rp, ta]
+        a = arr[i]
+        a.ctx = q.ctx._h
+        a.nframes = n
+        a.row_ptr = ctypes.cast(rp, POINTER(c_void_p))
+        a.toa = ctypes.cast(ta, POINTER(c_void_p))
+        a.state[0] = q.states[0].c()
+        a.state[1] = q.states[1].c()
+        a.out = q.out.c()
+        a.pi_in = _ptr(q.pi_in, torch.float32)
+        a.faulty = _ptr(q.faulty, torch.uint8)
+        a.chunk_rows = int(q.chunk_rows)
+    return arr, keep
+
+
+def batch_run_noalloc(seqs, spin_limit: int = 0, blocks: int = 0, stream=None):
+    """Run a batch once with no device allocation (r3d_batch_run_noalloc):
+    the tables live in the library's static per-GPU scratch array. Device
+    errors go to the first sequence's context (``last_device_status``)."""
+    lib = load()
+    seqs = list(seqs)
+    arr, keep = _c_sequences(seqs)
+    opt = CBatchOptions(int(spin_limit), int(blocks))
+    _check(lib.r3d_batch_run_noalloc(arr, len(seqs), byref(opt), _stream(stream)),
+           "r3d_batch_run_noalloc")
+    del keep
+
+
 class Batch:
     """An r3d_batch: many sequences in one persistent launch, captured once
     into a graph and replayed by ``launch``."""
@@ -431,24 +471,7 @@ class Batch:
     def __init__(self, seqs, spin_limit: int = 0, blocks: int = 0):
         lib = load()
         self.seqs = list(seqs)
-        arr = (CSequence * len(self.seqs))()
-        self._keep = []
-        for i, q in enumerate(self.seqs):
-            n = len(q.frames)
-            rp = (c_void_p * n)(*[_ptr(f[0], torch.int32) for f in q.frames])
-            ta = (c_void_p * n)(*[_ptr(f[1], torch.int16) for f in q.frames])
-            self._keep += [rp, ta]
-            a = arr[i]
-            a.ctx = q.ctx._h
-            a.nframes = n
-            a.row_ptr = ctypes.cast(rp, POINTER(c_void_p))
-            a.toa = ctypes.cast(ta, POINTER(c_void_p))
-            a.state[0] = q.states[0].c()
-            a.state[1] = q.states[1].c()
-            a.out = q.out.c()
-            a.pi_in = _ptr(q.pi_in, torch.float32)
-            a.faulty = _ptr(q.faulty, torch.uint8)
-            a.chunk_rows = int(q.chunk_rows)
+        arr, self._keep = _c_sequences(self.seqs)
         opt = CBatchOptions(int(spin_limit), int(blocks))
         h = c_void_p()
         _check(lib.r3d_batch_create(arr, len(self.seqs), byref(opt), byref(h)),

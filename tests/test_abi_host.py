@@ -136,6 +136,11 @@ def test_batch_entry_points_reject_bad_arguments(r3d):
     assert lib.r3d_batch_launch(None, None) == -1
     assert lib.r3d_batch_status(None, None) == -1
     lib.r3d_batch_destroy(None)
+    # the allocation-free run checks its arguments before any HIP call
+    assert lib.r3d_batch_run_noalloc(None, 1, None, None) == -1
+    assert lib.r3d_batch_run_noalloc(seqs, 0, None, None) == -1
+    assert lib.r3d_batch_run_noalloc(seqs, 1, None, None) == -1  # NULL context
+    assert lib.r3d_batch_run_noalloc(seqs, 1, ctypes.byref(bad), None) == -1
 
 
 def test_filter_entry_points_reject_bad_arguments(r3d):
