@@ -12,10 +12,14 @@ frame).
 Inputs are drawn on the device before timing (15 GiB resident in HBM).
 
 Prints one JSON line with the matrix-core form's pixel-frames/s, the plain
-fp32 form's rate on the same workload and entry point, the roofline of the
-tile kernel (HBM-bound: algorithmic bytes per launch over the average launch
-time, measured with events on the launch stream) and the FP64 CPU oracle's
-rate on a bounded sample.
+fp32 form's rate on the same workload, entry point, steps and warm-up (with
+its FLOP rate against the fp32 vector peak), the roofline of the tile kernel
+(HBM-bound: algorithmic bytes per launch over the average launch time,
+measured with events on the launch stream), the accuracy of the timed run's
+last frame against the FP64 CPU oracle stepped from the GPU's own input
+state, and the oracle's rate on a bounded sample (64x64 x 3 frames of the
+same recipe, on single-threaded worker processes forked before the GPU is
+used).
 
 ``--traffic-probe`` runs 4 frames of the sequence call, then a 512 MiB
 device copy, and exits: the driver of the rocprofv3 counter runs whose
@@ -32,6 +36,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pixel-frames/sec (cost+argmax+fusion) at 256×256×4096 bins; MFMA/batched vs plain"
 HBM_PEAK_GBS = 8000.0
+# fp32 FMAs without packing: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
 
 
 def algorithmic_bytes_per_pixel_frame(T: int) -> int:
@@ -148,18 +154,22 @@ def run_gpu(args):
         # launches of the tile kernel per step: one per frame
         launches = F
         launch_ms = sum(a.elapsed_time(b) for a, b in evs) / (steps * launches)
-        return wall, launch_ms
+        return wall, launch_ms, (ctx, st, out)
 
     prec = r3d.PRECISIONS[args.precision]
-    wall, launch_ms = timed(prec, args.steps, args.warmup)
+    wall, launch_ms, last = timed(prec, args.steps, args.warmup)
     ms_per_step = 1e3 * wall / args.steps
     value = P * F * args.steps / wall
     plain = None
     if args.plain_steps > 0 and prec != r3d.R3D_FP32:
-        # the plain form (fp32 vector FMAs) through the per-frame entry point
-        pw, pl = timed(r3d.R3D_FP32, args.plain_steps, 1, per_frame=True)
-        plain = dict(value=P * F * args.plain_steps / pw, ms_per_step=1e3 * pw / args.plain_steps,
-                     launch_ms=pl, precision="fp32", entry="r3d_step_hist per frame")
+        # the plain form (fp32 vector FMAs, no matrix cores) through the same
+        # sequence call, steps and warm-up
+        pw, pl, _ = timed(r3d.R3D_FP32, args.steps, args.warmup)
+        flop = 2.0 * P * wl.D * wl.W  # the full correlation: one FMA per pixel, depth and tap
+        tf = flop / (pl * 1e-3) / 1e12
+        plain = dict(value=P * F * args.steps / pw, ms_per_step=1e3 * pw / args.steps,
+                     launch_ms=pl, precision="fp32", entry="r3d_run_hist (one launch per frame)",
+                     tflops=tf, valu_frac=tf / FP32_VALU_PEAK_TFLOPS)
     # algorithmic bytes of one frame per launch
     bytes_launch = algorithmic_bytes_per_pixel_frame(T) * P
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
@@ -168,14 +178,15 @@ def run_gpu(args):
                 traffic=measured_traffic(args.precision, F),
                 kernel=f"k_tile_step (one launch per frame, {F}-frame sequence call)",
                 launch_ms=round(launch_ms, 5), bytes_per_launch=round(bytes_launch))
-    sample_hist = None
-    if not args.no_cpu_baseline:
-        r = args.cpu_rows
-        sample_hist = [wl.hist[n].reshape(wl.rows, wl.cols, T)[:r, :r].reshape(r * r, T)
-                       .float().cpu().numpy() for n in range(args.cpu_frames)]
+    # what the accuracy check of the timed run needs: frame F-1's histograms,
+    # its input state (the sequence call leaves it in the second buffer) and
+    # its outputs
+    ctx, st, out = last
+    tail = dict(hist=wl.hist[F - 1], state_in=st[(F - 1) % 2], state_out=st[F % 2], out=out,
+                frame=F - 1)
     res = dict(value=value, ms_per_step=ms_per_step, plain=plain, roofline=roof, P=P, F=F, T=T,
-               params=params)
-    return res, sample_hist
+               params=params, tail=tail)
+    return res
 
 
 def run_batched(args):
@@ -293,20 +304,118 @@ def run_grad(args):
                          "IRF taps, sigma_rw2, nu[9]")
 
 
-def cpu_baseline(params, sample_hist, rows):
-    import numpy as np
+# ---------------------------------------------------------------------------
+# the oracle leg: the FP64 CPU oracle timed on a bounded sample of the
+# workload (cpu_baseline), and the accuracy of the timed GPU run's last frame
+# against it
+# ---------------------------------------------------------------------------
+def _oracle_task(task):
+    """One worker task: oracle.step for a chunk of pixels from a given full
+    state. Returns the chunk's outputs and new state."""
     import oracle
-    p = dict(params)
-    p["rows"] = p["cols"] = rows
-    model = oracle.Model.from_params(p)
-    frames = [h.astype(np.int64) for h in sample_hist]
-    t0 = time.perf_counter()
-    oracle.run(model, frames)
-    dt = time.perf_counter() - t0
-    n = rows * rows * len(frames)
-    return dict(value=round(n / dt, 2), unit="pixel-frames/s", cores=1, kind="oracle",
-                sample=f"{rows}x{rows} crop x {len(frames)} frames of the same workload "
-                       f"({n} pixel-frames, {dt:.1f} s, single thread)")
+    params, state, z, pix = task
+    model = oracle.Model.from_params(params)
+    new, out = oracle.step(model, oracle.State(*state), z, pixels=pix)
+    return pix, tuple(a[pix] for a in (new.m, new.v, new.pi, new.b)), out
+
+
+class OracleLeg:
+    """A pool of CPU workers forked before the GPU is touched (each runs the
+    oracle single-threaded on chunks of pixels of one frame; a frame's
+    chunks all start from the same full previous state, so the chunked run
+    equals the whole-frame run)."""
+
+    def __init__(self, workers: int):
+        import multiprocessing as mp
+        self.workers = workers
+        self.pool = mp.get_context("fork").Pool(workers)
+
+    def close(self):
+        self.pool.close()
+        self.pool.join()
+
+    def step(self, params, state, z, pix, chunk):
+        import numpy as np
+        tasks = [(params, state, z[i:i + chunk], pix[i:i + chunk]) for i in range(0, len(pix), chunk)]
+        res = self.pool.map(_oracle_task, tasks)
+        P = params["rows"] * params["cols"]
+        new = [np.full(P, np.nan) for _ in range(4)]
+        outs = {}
+        for p, st, o in res:
+            for a, b in zip(new, st):
+                a[p] = b
+            for k, v in o.items():
+                if isinstance(v, np.ndarray) and v.shape[:1] == p.shape:
+                    outs.setdefault(k, []).append(v)
+        return tuple(new), {k: np.concatenate(v) for k, v in outs.items()}
+
+    def baseline(self, rows: int, frames: int):
+        """The oracle on a rows x rows crop of the workload's recipe (drawn on
+        the host) for ``frames`` frames from the initial state."""
+        import numpy as np
+        import oracle
+        import synth
+        wl = synth.config4(seed=1, device="cpu", frames=frames, rows=rows, cols=rows)
+        params = wl.params()
+        model = oracle.Model.from_params(params)
+        s0 = oracle.init_state(model)
+        state = (s0.m, s0.v, s0.pi, s0.b)
+        pix = np.arange(wl.P)
+        zs = [wl.hist[n].float().numpy().astype(np.int64) for n in range(frames)]
+        t0 = time.perf_counter()
+        for n in range(frames):
+            state, _ = self.step(params, state, zs[n], pix, chunk=max(1, wl.P // (4 * self.workers)))
+        dt = time.perf_counter() - t0
+        n = wl.P * frames
+        return dict(value=round(n / dt, 2), unit="pixel-frames/s", cores=self.workers,
+                    kind="oracle",
+                    sample=f"{rows}x{rows} crop x {frames} frames of the same workload recipe "
+                           f"(T=4096, drawn on the host; {n} pixel-frames, {dt:.1f} s on "
+                           f"{self.workers} single-threaded worker processes)")
+
+    def accuracy(self, params, tail, npix: int):
+        """The timed run's last frame on ``npix`` sampled pixels (corners and
+        seeded random pixels), stepped by the oracle from the GPU's own input
+        state of that frame: argmax disagreements beyond the 1e-3 nat margin,
+        and the largest posterior-mean and variance errors over their
+        tolerances (1e-4 * max(1, sd) bins plus half an fp32 ulp of the
+        depth, the stored output's own rounding; 1e-3 relative)."""
+        import numpy as np
+        import oracle
+        P = params["rows"] * params["cols"]
+        rng = np.random.default_rng(7)
+        pix = np.unique(np.concatenate([[0, params["cols"] - 1, P - params["cols"], P - 1],
+                                        rng.choice(P, npix - 4, replace=False)]))
+        idx = __import__("torch").as_tensor(pix, device=tail["hist"].device)
+        z = tail["hist"].index_select(0, idx).float().cpu().numpy().astype(np.int64)
+        s_in = tuple(getattr(tail["state_in"], k).double().cpu().numpy() for k in ("m", "v", "pi", "b"))
+        _, ref = self.step(params, s_in, z, pix, chunk=max(1, len(pix) // self.workers))
+        f = tail["frame"]
+        o = tail["out"]
+        off = f * P
+        am = o.argmax[off:off + P].cpu().numpy()[pix].astype(np.int64)
+        mean = tail["state_out"].m.cpu().numpy()[pix].astype(np.float64)
+        var = o.var[off:off + P].cpu().numpy()[pix].astype(np.float64)
+        sure = ref["margin"] > 1e-3
+        sd = np.sqrt(np.maximum(ref["var"], 0.0))
+        same = am == ref["argmax"]
+        model = oracle.Model.from_params(params)
+        st = oracle.State(*s_in)
+        near = (~sure) & ~same
+        outside = 0
+        if near.any():
+            logw, mu, vv = oracle.prior_components(model, st, pix[near])
+            L = oracle.log_prior(logw, mu, vv, model.grid) + oracle.cost_from_histogram(z[near], model)
+            gap = L.max(axis=1) - L[np.arange(L.shape[0]), am[near] - model.d_lo]
+            outside = int(np.sum(gap > 1e-3))
+        return dict(frame=int(f), pixels=int(len(pix)),
+                    argmax_mismatch_beyond_margin=int(np.sum(sure & ~same)),
+                    argmax_outside_tie_set=outside,
+                    max_mean_err_over_tol=round(float(np.max(np.abs(mean - ref["mean"]) / (
+                        1e-4 * np.maximum(1.0, sd)
+                        + 0.5 * np.spacing(np.abs(ref["mean"]).astype(np.float32)).astype(np.float64)))), 4),
+                    max_var_err_over_tol=round(float(np.max(np.abs(var - ref["var"]) / (1e-3 * np.maximum(1.0, ref["var"])))), 4),
+                    rule="oracle stepped from the GPU's input state of the frame; pass = 0, 0, <= 1, <= 1")
 
 
 def main():
@@ -318,8 +427,10 @@ def main():
     ap.add_argument("--frames", type=int, default=30)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=20)
-    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-rows", type=int, default=64)
+    ap.add_argument("--cpu-frames", type=int, default=3)
+    ap.add_argument("--cpu-workers", type=int, default=16)
+    ap.add_argument("--accuracy-pixels", type=int, default=256)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--tune-cache", default="")
@@ -332,14 +443,25 @@ def main():
               "(multi-GPU sharding is a design note, not implemented); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    # the oracle's workers are single-threaded processes
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
     if args.traffic_probe:
         traffic_probe()
         return
-    res, sample = run_gpu(args)
+    leg = cpu = accuracy = None
+    if not args.no_cpu_baseline:
+        # forked before anything touches the GPU; timed before the GPU legs
+        workers = max(1, min(args.cpu_workers, len(os.sched_getaffinity(0))))
+        leg = OracleLeg(workers)
+        cpu = leg.baseline(args.cpu_rows, args.cpu_frames)
+    res = run_gpu(args)
+    if leg is not None:
+        accuracy = leg.accuracy(res["params"], res["tail"], args.accuracy_pixels)
+        leg.close()
+    res.pop("tail")
     batched = None if args.no_batched else run_batched(args)
     gradient = None if args.no_grad else run_grad(args)
-    cpu = cpu_baseline(res["params"], sample, args.cpu_rows) if sample is not None else None
     line = dict(
         metric=METRIC, value=round(res["value"], 1), unit="pixel-frames/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=round(res["ms_per_step"], 4),
@@ -353,8 +475,13 @@ def main():
         plain_fp32=(None if res["plain"] is None else
                     dict(value=round(res["plain"]["value"], 1),
                          ms_per_step=round(res["plain"]["ms_per_step"], 3),
+                         launch_ms=round(res["plain"]["launch_ms"], 4),
+                         entry=res["plain"]["entry"],
+                         tflops=round(res["plain"]["tflops"], 2),
+                         valu_frac=round(res["plain"]["valu_frac"], 4),
                          speedup=round(res["value"] / res["plain"]["value"], 3))),
-        roofline=res["roofline"], cpu_baseline=cpu, batched=batched, gradient=gradient)
+        roofline=res["roofline"], accuracy=accuracy, cpu_baseline=cpu, batched=batched,
+        gradient=gradient)
     print(json.dumps(line), flush=True)
 
 

@@ -5,7 +5,8 @@ Comparison rules (see the test docstrings for where each applies):
 * argmax: identical wherever the oracle's log-margin of d* over the
   runner-up exceeds ``margin``; elsewhere the GPU index must lie within
   ``margin`` of the oracle's maximum in the oracle's log pseudo-posterior;
-* posterior mean: |gpu - oracle| <= mean_rel * max(1, oracle posterior sd);
+* posterior mean: |gpu - oracle| <= mean_rel * max(1, oracle posterior sd)
+  + half an fp32 ulp of the oracle's mean (the output is stored in fp32);
 * variance: |gpu - oracle| <= var_rel * max(1, oracle variance);
 * reflectivity / background (where the argmax agrees):
   |gpu - oracle| <= int_rel * max(1, |oracle|);
@@ -17,6 +18,12 @@ import numpy as np
 import torch
 
 import oracle
+
+
+def fp32_half_ulp(x) -> np.ndarray:
+    """Half the fp32 spacing at |x|: the rounding of a result delivered in
+    fp32 (1.2e-4 bins for depths in [2048, 4096))."""
+    return 0.5 * np.spacing(np.abs(np.asarray(x, np.float64)).astype(np.float32)).astype(np.float64)
 
 
 def frame_hist(frame, T, pixels=None):
@@ -42,15 +49,20 @@ def gpu_outputs_np(out) -> dict:
     return d
 
 
-def oracle_log_posterior(model, state, z, pixels):
+def oracle_log_posterior(model, state, z, pixels, faulty=None):
+    """The oracle's log pseudo-posterior on the grid; a faulty pixel has no
+    observation, so its posterior is the prior alone (Sec. III-B)."""
     logw, mean, var = oracle.prior_components(model, state, np.asarray(pixels))
     logf = oracle.log_prior(logw, mean, var, model.grid)
-    return logf + oracle.cost_from_histogram(z, model)
+    ell = oracle.cost_from_histogram(z, model)
+    if faulty is not None:
+        ell[np.asarray(faulty, bool)[np.asarray(pixels)]] = 0.0
+    return logf + ell
 
 
 def compare(gpu: dict, ref: dict, *, model=None, state=None, z=None, pixels=None,
             margin=1e-3, mean_rel=1e-4, var_rel=1e-3, int_rel=1e-3, check_aux=True,
-            gpu_mean=None, label=""):
+            gpu_mean=None, faulty=None, label=""):
     """Assert GPU outputs (numpy dict, indexed like ``ref``) match the oracle.
     Returns a small report dict."""
     am_g = np.asarray(gpu["argmax"]).astype(np.int64)
@@ -60,14 +72,14 @@ def compare(gpu: dict, ref: dict, *, model=None, state=None, z=None, pixels=None
     assert n_bad == 0, f"{label}: {n_bad} argmax mismatches with margin > {margin}"
     near = (~sure) & (am_g != am_o)
     if np.any(near) and model is not None:
-        L = oracle_log_posterior(model, state, z[near], np.asarray(pixels)[near])
+        L = oracle_log_posterior(model, state, z[near], np.asarray(pixels)[near], faulty)
         idx = am_g[near] - model.d_lo
         gap = L.max(axis=1) - L[np.arange(L.shape[0]), idx]
         assert np.all(gap <= margin), f"{label}: near-tie argmax outside the tie set"
     sd = np.sqrt(np.maximum(ref["var"], 0.0))
     mean = gpu_mean if gpu_mean is not None else gpu["mean"]
     err_m = np.abs(np.asarray(mean, np.float64) - ref["mean"])
-    tol_m = mean_rel * np.maximum(1.0, sd)
+    tol_m = mean_rel * np.maximum(1.0, sd) + fp32_half_ulp(ref["mean"])
     assert np.all(err_m <= tol_m), (
         f"{label}: mean error {np.max(err_m / tol_m):.3g}x tolerance "
         f"(worst pixel {int(np.argmax(err_m / tol_m))})")

@@ -1,0 +1,111 @@
+"""Parity of the benchmark's configuration at full size: 256x256 pixels,
+T = 4096 fp16 histograms, 30 frames of the moving scene, the split fp16
+matrix-core engine (and the fp32 vector engine on three frames).
+
+The GPU runs its own chain over all 30 frames (one step call per frame).
+At frames 0, 1, 2, 10, 20, 28 and 29 the GPU's input state (fp32, cast to
+float64) is handed to the oracle, which steps the sampled pixels of that
+frame from exactly that state; so every sampled output is compared with the
+oracle on identical inputs, at the stated tolerances: argmax identical
+where the oracle's margin exceeds 1e-3 nats, else inside the oracle's tie
+set (log posterior within 1e-3 of its maximum); posterior mean within
+1e-4 * max(1, sd) bins plus half an fp32 ulp of the depth (the stored
+output's own rounding: 1.2e-4 bins above depth 2048); variance 1e-3
+relative; reflectivity and background
+1e-3 relative; next prior presence 1e-5 absolute.
+
+Sampled pixels per frame (about 290): the four corners, 8 random pixels on
+each image edge, the two aligned 4x4 blocks with the most depth
+discontinuities inside them (one on the square moving right, one on the
+disk moving left) and 224 random pixels elsewhere."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity_util import compare, frame_hist, gpu_outputs_np
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+FRAMES = (0, 1, 2, 10, 20, 28, 29)
+
+
+def boundary_blocks(depth: np.ndarray):
+    """Top-left corners of the aligned 4x4 block with the most internal
+    depth steps (> 50 bins between 4-neighbours) in the upper half (the
+    square) and in the lower half (the disk)."""
+    rows, cols = depth.shape
+    step = np.zeros_like(depth, dtype=bool)
+    step[:, 1:] |= np.abs(np.diff(depth, axis=1)) > 50
+    step[1:, :] |= np.abs(np.diff(depth, axis=0)) > 50
+    cnt = step.reshape(rows // 4, 4, cols // 4, 4).sum(axis=(1, 3))
+    half = rows // 8
+    out = []
+    for lo, hi in ((0, half), (half, rows // 4)):
+        sub = cnt[lo:hi]
+        br, bc = np.unravel_index(np.argmax(sub), sub.shape)
+        assert sub[br, bc] > 0
+        out.append((4 * (br + lo), 4 * bc))
+    return out
+
+
+def sample_pixels(wl, n, rng):
+    rows, cols = wl.rows, wl.cols
+    depth = wl.depth_true[n].reshape(rows, cols).cpu().numpy().astype(np.int64)
+    pix = [0, cols - 1, (rows - 1) * cols, rows * cols - 1]
+    pix += list(rng.choice(cols, 8, replace=False))                        # top row
+    pix += list((rows - 1) * cols + rng.choice(cols, 8, replace=False))    # bottom row
+    pix += list(rng.choice(rows, 8, replace=False) * cols)                 # left column
+    pix += list(rng.choice(rows, 8, replace=False) * cols + cols - 1)      # right column
+    for r0, c0 in boundary_blocks(depth):
+        pix += [(r0 + i) * cols + c0 + j for i in range(4) for j in range(4)]
+    pix = set(int(p) for p in pix)
+    while len(pix) < 290:
+        pix.add(int(rng.integers(wl.P)))
+    return np.array(sorted(pix))
+
+
+def gpu_chain(lib, wl, prec, keep):
+    """Run all frames on the GPU; return, for each frame in ``keep``, the
+    input state (float64 oracle State), the outputs and the next state's
+    mean (numpy)."""
+    ctx = lib.Context(wl.params(), prec)
+    st = [lib.State.empty(wl.P, DEV), lib.State.empty(wl.P, DEV)]
+    ctx.state_init(st[0])
+    out = lib.Outputs.empty(wl.P, DEV)
+    saved = {}
+    for n in range(wl.nframes):
+        prev, nxt = st[n % 2], st[(n + 1) % 2]
+        if n in keep:
+            s_in = oracle.State(*(t.double().cpu().numpy() for t in (prev.m, prev.v, prev.pi, prev.b)))
+        ctx.step_hist(wl.hist[n], prev, nxt, out)
+        if n in keep:
+            g = gpu_outputs_np(out)
+            g["mean"] = nxt.m.cpu().numpy()
+            saved[n] = (s_in, g)
+    assert ctx.last_device_status() == 0
+    return saved
+
+
+@pytest.fixture(scope="module")
+def workload():
+    return synth.config4(device=DEV, frames=30)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,frames", [("fp16x2", FRAMES), ("fp32", (1, 10, 29))])
+def test_full_size_state_forced(lib, workload, prec, frames):
+    wl = workload
+    model = oracle.Model.from_params(wl.params())
+    saved = gpu_chain(lib, wl, prec, set(frames))
+    rng = np.random.default_rng(2024)
+    for n in frames:
+        s_in, g = saved[n]
+        pix = sample_pixels(wl, n, rng)
+        z = frame_hist(wl.hist[n], wl.T, pix)
+        _, ref = oracle.step(model, s_in, z, pixels=pix)
+        sub = {k: v[pix] for k, v in g.items()}
+        rep = compare(sub, ref, model=model, state=s_in, z=z, pixels=pix, mean_rel=1e-4,
+                      var_rel=1e-3, int_rel=1e-3, label=f"{prec} frame {n}")
+        print(prec, n, len(pix), rep, flush=True)

@@ -109,11 +109,20 @@ def test_single_frame_config1(lib):
     print(rep)
 
 
-def test_video_teacher_forced(lib):
+@pytest.mark.parametrize("case", ["plain", "faulty_pi"])
+def test_video_teacher_forced(lib, case):
     """Every frame starts from the oracle's own state (cast to fp32), so each
-    step is compared in isolation: 40x40 crop of the video workload."""
+    step is compared in isolation: 40x40 crop of the video workload; in the
+    faulty_pi case with caller-supplied presence probabilities and 10 %
+    faulty pixels (Sec. III-B)."""
     wl = synth.config2(frames=4, rows=40, cols=40)
-    o, states, model = run_oracle(wl, wl.frames)
+    pi_in = faulty = None
+    if case == "faulty_pi":
+        g0 = torch.Generator().manual_seed(23)
+        pi_in = torch.rand(len(wl.frames), wl.P, generator=g0)
+        faulty = (torch.rand(wl.P, generator=g0) < 0.1).to(torch.uint8)
+    o, states, model = run_oracle(wl, wl.frames, pi_in=pi_in, faulty=faulty)
+    fl = None if faulty is None else faulty.numpy().astype(bool)
     ctx = lib.Context(wl.params())
     for n, fr in enumerate(wl.frames):
         st = states[n]
@@ -121,12 +130,14 @@ def test_video_teacher_forced(lib):
                            for a in (st.m, st.v, st.pi, st.b)))
         nxt = lib.State.empty(wl.P, DEV)
         out = lib.Outputs.empty(wl.P, DEV)
-        ctx.step_csr(*to_dev(fr), prev, nxt, out)
+        ctx.step_csr(*to_dev(fr), prev, nxt, out,
+                     pi_in=None if pi_in is None else pi_in[n].to(DEV),
+                     faulty=None if faulty is None else faulty.to(DEV))
         g = gpu_outputs_np(out)
         g["mean"] = nxt.m.cpu().numpy()
         z = frame_hist(fr, wl.T)
-        rep = compare(g, o[n], model=model, state=st, z=z, pixels=np.arange(wl.P),
-                      label=f"frame {n}")
+        rep = compare(g, o[n], model=model, state=st, z=z, pixels=np.arange(wl.P), faulty=fl,
+                      label=f"{case} frame {n}")
         print(n, rep)
     assert ctx.last_device_status() == 0
 

@@ -50,26 +50,39 @@ def test_cost_tile_matches_oracle(lib, prec, shape):
     np.testing.assert_allclose(ell, ref, rtol=rel, atol=rel * max(1.0, ref.max()))
 
 
+@pytest.mark.parametrize("case", ["plain", "faulty_pi"])
 @pytest.mark.parametrize("prec", ENGINES)
-def test_step_tile_teacher_forced(lib, prec):
+def test_step_tile_teacher_forced(lib, prec, case):
     """Each frame starts from the oracle's state (cast to fp32): 12x20 crop of
-    the 4096-bin histogram workload, 3 frames."""
+    the 4096-bin histogram workload, 3 frames; in the faulty_pi case every
+    frame has caller-supplied presence probabilities and 10 % of the pixels
+    are faulty (their posterior is the prior, Sec. III-B)."""
     wl = hist_workload()
     model = oracle.Model.from_params(wl.params())
     ctx = lib.Context(wl.params(), prec)
     st = oracle.init_state(model)
+    pi_in = faulty = None
+    if case == "faulty_pi":
+        g0 = torch.Generator().manual_seed(17)
+        pi_in = torch.rand(wl.nframes, wl.P, generator=g0)
+        faulty = (torch.rand(wl.P, generator=g0) < 0.1).to(torch.uint8)
+    fl = None if faulty is None else faulty.numpy().astype(bool)
     for n in range(wl.nframes):
         z = frame_hist(wl.hist[n], wl.T)
-        new, ref = oracle.step(model, st, z)
+        pin = None if pi_in is None else pi_in[n].numpy().astype(np.float64)
+        new, ref = oracle.step(model, st, z, pi_in=pin, faulty=fl)
         prev = lib.State(*(torch.tensor(a, dtype=torch.float32, device=DEV)
                            for a in (st.m, st.v, st.pi, st.b)))
         nxt = lib.State.empty(wl.P, DEV)
         out = lib.Outputs.empty(wl.P, DEV)
-        ctx.step_hist(wl.hist[n].to(DEV).contiguous(), prev, nxt, out)
+        ctx.step_hist(wl.hist[n].to(DEV).contiguous(), prev, nxt, out,
+                      pi_in=None if pi_in is None else pi_in[n].to(DEV),
+                      faulty=None if faulty is None else faulty.to(DEV))
         g = gpu_outputs_np(out)
         g["mean"] = nxt.m.cpu().numpy()
-        rep = compare(g, ref, model=model, state=st, z=z, pixels=np.arange(wl.P),
-                      label=f"{prec} frame {n}", **tol_for(prec))
+        rep = compare(g, ref, model=model, state=st, z=z, pixels=np.arange(wl.P), faulty=fl,
+                      label=f"{prec} {case} frame {n}", **tol_for(prec))
+        np.testing.assert_allclose(nxt.pi.cpu().numpy(), new.pi, atol=1e-6)
         print(prec, n, rep)
         st = new
     assert ctx.last_device_status() == 0
