@@ -51,6 +51,8 @@ typedef _Float16 half2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRingT = 256;            // LDS ring per pixel (fp16 bins), VALU engine
+constexpr int kRingStride = kRingT + 8;  // its row stride: 16 bytes of padding spread the pixels
+                                         // over the LDS banks
 constexpr float kCullMargin2 = 64.f;  // log2 units: skipped weights below 2^-64 of the largest
 constexpr float kLog2Nine = 3.16992500144231236f;
 constexpr float kLiveGap = 40.f;        // log2 units
@@ -189,32 +191,51 @@ __device__ __forceinline__ const half8& a_op(const half8* sA, int nbp, int part,
   return sA[((part * 2 + tau) * nbp + b) * 64 + lane];
 }
 
-// fp32 cost of tile tau of pair m from the LDS ring (VALU engine): the lane
-// computes its 4 depths d = d_lo + 32 m + 16 tau + 4 g + q.
-__device__ __forceinline__ floatx4 valu_tile(const DevModel& M, const _Float16* ring_lds, int i16,
-                                             int g, int m, int tau) {
-  const int t0 = M.d_lo + 32 * m + 16 * tau + 4 * g - M.c;
-  const _Float16* rp = ring_lds + i16 * kRingT;
-  float a0 = (float)rp[(t0 + 0) & (kRingT - 1)];
-  float a1 = (float)rp[(t0 + 1) & (kRingT - 1)];
-  float a2 = (float)rp[(t0 + 2) & (kRingT - 1)];
-  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int j = 0; j < M.W; ++j) {
-    const float a3 = (float)rp[(t0 + j + 3) & (kRingT - 1)];
-    const float hj = M.h[j];
-    acc[0] = fmaf(hj, a0, acc[0]);
-    acc[1] = fmaf(hj, a1, acc[1]);
-    acc[2] = fmaf(hj, a2, acc[2]);
-    acc[3] = fmaf(hj, a3, acc[3]);
-    a0 = a1;
-    a1 = a2;
-    a2 = a3;
+// fp32 cost of both tiles of pair m from the LDS ring (VALU engine): the
+// lane computes its depths d = d_lo + 32 m + 16 tau + 4 g + q (q < 4) of
+// tile tau as register blocks. With s = (d_lo - c) mod 4 and the taps
+// shifted by s (hs[j'] = irf^beta[j' - s], zero outside the W taps, padded
+// to a multiple of 4), every window starts on a multiple of 4 bins: each
+// step takes 4 taps from one broadcast LDS read and 4 new bins of each
+// window from one 8-byte LDS read, for 32 FMAs. Every accumulator adds its
+// taps in increasing order, one FMA each, as the definition reads.
+__device__ __forceinline__ int valu_shift(const DevModel& M) { return ((M.d_lo - M.c) % 4 + 4) % 4; }
+__device__ __forceinline__ int valu_taps(const DevModel& M) { return (M.W + valu_shift(M) + 3) & ~3; }
+
+__device__ __forceinline__ void valu_pair(const DevModel& M, const float* hs, const _Float16* ring_lds,
+                                          int i16, int g, int m, floatx4& c0, floatx4& c1) {
+  typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+  const int s = valu_shift(M), wp = valu_taps(M);
+  const int ta = M.d_lo - M.c + 32 * m + 4 * g - s;  // a multiple of 4
+  const _Float16* rp = ring_lds + i16 * kRingStride;
+  auto ld4 = [&](int t) __attribute__((always_inline)) -> floatx4 {
+    const half4 v = *reinterpret_cast<const half4*>(rp + (t & (kRingT - 1)));
+    return floatx4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+  };
+  floatx4 x0 = ld4(ta), x1 = ld4(ta + 16);
+  floatx4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
+#pragma unroll 2
+  for (int jb = 0; jb < wp; jb += 4) {
+    const floatx4 y0 = ld4(ta + jb + 4), y1 = ld4(ta + jb + 20);
+    const floatx4 h = *reinterpret_cast<const floatx4*>(hs + jb);
+    const float w0[8] = {x0[0], x0[1], x0[2], x0[3], y0[0], y0[1], y0[2], y0[3]};
+    const float w1[8] = {x1[0], x1[1], x1[2], x1[3], y1[0], y1[1], y1[2], y1[3]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a0[q] = fmaf(h[k], w0[q + k], a0[q]);
+        a1[q] = fmaf(h[k], w1[q + k], a1[q]);
+      }
+    x0 = y0;
+    x1 = y1;
   }
-  return acc;
+  c0 = a0;
+  c1 = a1;
 }
 
 __device__ __forceinline__ void ring_store(_Float16* ring_lds, int i16, int g, int kb, half8 v) {
-  *reinterpret_cast<half8*>(ring_lds + i16 * kRingT + ((32 * kb + 8 * g) & (kRingT - 1))) = v;
+  *reinterpret_cast<half8*>(ring_lds + i16 * kRingStride + ((32 * kb + 8 * g) & (kRingT - 1))) = v;
 }
 
 // Exact cost of both tiles of pair m from its NBP blocks: fp16 hi (and lo)
@@ -242,8 +263,7 @@ __device__ __forceinline__ void pair_cost(const DevModel& M, const half8* sA, co
       c1 = h1;
     }
   } else {
-    c0 = valu_tile(M, ring_lds, lane & 15, lane >> 4, m, 0);
-    c1 = valu_tile(M, ring_lds, lane & 15, lane >> 4, m, 1);
+    valu_pair(M, reinterpret_cast<const float*>(sA), ring_lds, lane & 15, lane >> 4, m, c0, c1);
   }
 }
 
@@ -958,8 +978,7 @@ __device__ __forceinline__ void step_wave(const DevModel& M, const TileGeom& G, 
                 a1 = mfma16(Ahi[1][b], blk[b], a1);
               }
             } else {
-              a0 = valu_tile(M, ring_lds, i16, g, m, 0);
-              a1 = valu_tile(M, ring_lds, i16, g, m, 1);
+              valu_pair(M, reinterpret_cast<const float*>(sA), ring_lds, i16, g, m, a0, a1);
             }
             // a pixel whose cost in this pair may exceed its margin needs the
             // pair evaluated with every component (the cost is >= 0: compare
@@ -1079,7 +1098,15 @@ __device__ __forceinline__ void tile_prologue(const DevModel& M, const TileGeom&
     sh16[j] = M.h16hi[j];
     sh16[M.W + j] = M.h16lo[j];
   }
-  if constexpr (kEng != kEngValu) {
+  if constexpr (kEng == kEngValu) {
+    // the VALU engine's taps, shifted by (d_lo - c) mod 4 and zero-padded
+    float* hs = reinterpret_cast<float*>(smem + G.lds_a);
+    const int sh = ((M.d_lo - M.c) % 4 + 4) % 4, wp = (M.W + sh + 3) & ~3;
+    for (int j = threadIdx.x; j < wp; j += blockDim.x) {
+      const int k = j - sh;
+      hs[j] = (k >= 0 && k < M.W) ? M.h[k] : 0.f;
+    }
+  } else {
     __syncthreads();
     half8* sA = reinterpret_cast<half8*>(smem + G.lds_a);
     for (int e = threadIdx.x; e < 2 * 2 * NBP * 64; e += blockDim.x) {
@@ -1180,7 +1207,7 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
   const TileGeom& G0 = A.G[0];
   const int idx = blockIdx.x * 4 + wave;
   if (idx >= G0.nblk) return;
-  _Float16* ring_lds = reinterpret_cast<_Float16*>(smem + A.nb * A.lds_band) + wave * 16 * kRingT;
+  _Float16* ring_lds = reinterpret_cast<_Float16*>(smem + A.nb * A.lds_band) + wave * 16 * kRingStride;
 
   // photon count of each band (every block once) and count validation:
   // integers in [0, 2048]
@@ -1272,6 +1299,10 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
 
 static int floor_div(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
+// LDS bytes of the VALU engine's shifted taps (padded to a multiple of 4,
+// plus one spare group)
+static int valu_hs_bytes(const DevModel& M) { return ((4 * (M.W + 8) + 15) / 16) * 16; }
+
 bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
   if (M.T % 8 != 0) return false;
   G = TileGeom{};
@@ -1294,12 +1325,12 @@ bool tile_geometry(const DevModel& M, int engine, TileGeom& G) {
   // per wavefront: masks, component tile ranges, halo, components and (VALU
   // engine) the ring
   G.lds_a = ((12 * M.W + 15) / 16) * 16;  // irf, irf^beta (fp32), fp16 hi and lo
-  G.lds_fixed = G.lds_a + (engine == kEngValu ? 0 : 2 * 2 * G.nbp * 64 * 16);
+  G.lds_fixed = G.lds_a + (engine == kEngValu ? valu_hs_bytes(M) : 2 * 2 * G.nbp * 64 * 16);
   G.off_trange = ((4 * (G.mask_words + G.pair_words + 1) + 15) / 16) * 16;
   G.off_halo = G.off_trange + 80;
   G.off_comp = G.off_halo + kHaloBytes;
   G.off_ring = G.off_comp + kCompBytes;
-  G.lds_per_wave = G.off_ring + (engine == kEngValu ? 16 * kRingT * 2 : 0);
+  G.lds_per_wave = G.off_ring + (engine == kEngValu ? 16 * kRingStride * 2 : 0);
   G.waves = engine == kEngValu ? kWavesOf<kEngValu> : kWavesOf<kEngMfma16x2>;
   G.off_share = G.lds_fixed + G.waves * G.lds_per_wave;
   G.lds_total = G.off_share + kShareBytes;
@@ -1419,12 +1450,12 @@ hipError_t launch_mindiv(const DevModel* M, const uint16_t* const* hist, int nb,
   for (int l = 0; l < nb; ++l) {
     A.G[l].nbp = nbp;
     A.G[l].lda_band = ((12 * M[l].W + 15) / 16) * 16;
-    const int need = A.G[l].lda_band + (engine == kEngValu ? 0 : 2 * 2 * nbp * 64 * 16);
+    const int need = A.G[l].lda_band + (engine == kEngValu ? valu_hs_bytes(M[l]) : 2 * 2 * nbp * 64 * 16);
     band = need > band ? need : band;
   }
   for (int l = 0; l < nb; ++l) A.G[l].lds_a = A.G[l].lda_band;
   A.lds_band = band;
-  const size_t lds = (size_t)nb * band + (engine == kEngValu ? 4 * 16 * kRingT * 2 : 0);
+  const size_t lds = (size_t)nb * band + (engine == kEngValu ? 4 * 16 * kRingStride * 2 : 0);
   const int lds_max = M[0].lds_max > 0 ? M[0].lds_max : 65536;
   if (lds > (size_t)lds_max) return hipErrorInvalidValue;
   switch (engine) {

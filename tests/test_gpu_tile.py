@@ -31,7 +31,7 @@ def tol_for(prec):
     return dict(mean_rel=1e-4, var_rel=1e-3, int_rel=1e-3)
 
 
-@pytest.mark.parametrize("prec", ["fp16", "fp16x2"])
+@pytest.mark.parametrize("prec", ENGINES)
 @pytest.mark.parametrize("shape", ["c4crop", "tiny_offset"])
 def test_cost_tile_matches_oracle(lib, prec, shape):
     if shape == "c4crop":
