@@ -54,12 +54,10 @@ KERNEL_SRCS = ["paper_2004_09211_amd/csrc/k_tile.hip", "paper_2004_09211_amd/csr
 def measured_traffic(precision: str, frames: int):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     record, if it was taken on the kernel sources as they are now (else None)."""
-    import hashlib
     if precision != "fp16x2" or not os.path.exists(TRAFFIC_FILE):
         return None
     rec = json.load(open(TRAFFIC_FILE))
-    sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in KERNEL_SRCS))
-    if sha.hexdigest()[:16] != rec["kernel_src_sha"]:
+    if sources_sha(KERNEL_SRCS) != rec["kernel_src_sha"]:
         return None
     # one launch per frame: frame 0 (flat initial prior), frame 1 (the prior
     # left by frame 0), then F - 2 steady launches
@@ -68,6 +66,209 @@ def measured_traffic(precision: str, frames: int):
     total = (rec["frame0_launch_bytes"] + rec["frame1_launch_bytes"]
              + (frames - 2) * rec["steady_launch_bytes"])
     return round(total / frames)
+
+
+COUNTER_FILE = os.path.join(ROOT, "profiles", "counters_valu_lds.json")
+COUNTER_SRCS = ["paper_2004_09211_amd/csrc/k_tile.hip", "paper_2004_09211_amd/csrc/k_plain.hip",
+                "paper_2004_09211_amd/csrc/k_batch.hip", "paper_2004_09211_amd/csrc/k_adjoint.hip",
+                "paper_2004_09211_amd/csrc/r3d_device.hpp", "paper_2004_09211_amd/csrc/r3d_pixel.hpp",
+                "paper_2004_09211_amd/csrc/r3d_tile.hpp", "paper_2004_09211_amd/build.py"]
+
+
+def sources_sha(srcs) -> str:
+    import hashlib
+    return hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in srcs)).hexdigest()[:16]
+
+
+def recorded_counters(kernel: str):
+    """The committed rocprofv3 counter record of ``kernel`` (VALU issue
+    fraction and LDS figures per launch), if it was taken on the kernel
+    sources as they are now (else None)."""
+    if not os.path.exists(COUNTER_FILE):
+        return None
+    rec = json.load(open(COUNTER_FILE))
+    if rec.get("kernel_src_sha") != sources_sha(COUNTER_SRCS):
+        return None
+    return rec["kernels"].get(kernel)
+
+
+def counter_probe():
+    """Counter driver: a few launches of every measured kernel on its
+    workload (split-fp16 tile step, 3 frames of the 256x256x4096 histograms;
+    the fp32 vector form, 1 frame; the photon-list video, 5 frames; one pass
+    of the uneven batch with a fixed launch shape; one gradient pass)."""
+    import torch
+    import synth
+    from paper_2004_09211_amd import r3d
+    r3d.load()
+    dev = torch.device("cuda:0")
+    wl = synth.config4(seed=0, device=dev, frames=3)
+    for prec, nf in (("fp16x2", 3), ("fp32", 1)):
+        ctx = r3d.Context(wl.params(), prec)
+        st = [r3d.State.empty(wl.P, dev), r3d.State.empty(wl.P, dev)]
+        out = r3d.Outputs.empty(nf * wl.P, dev)
+        ctx.state_init(st[0])
+        ctx.run_hist([wl.hist[n] for n in range(nf)], st, out)
+        torch.cuda.synchronize()
+        assert ctx.last_device_status() == 0
+    del wl
+    wv = synth.config2(seed=0, device=dev, frames=5)
+    ctx = r3d.Context(wv.params())
+    st = [r3d.State.empty(wv.P, dev), r3d.State.empty(wv.P, dev)]
+    out = r3d.Outputs.empty(wv.P, dev)
+    ctx.state_init(st[0])
+    for n, f in enumerate(wv.frames):
+        ctx.step_csr(f.row_ptr, f.toa, st[n % 2], st[(n + 1) % 2], out)
+    torch.cuda.synchronize()
+    assert ctx.last_device_status() == 0
+    wls = synth.config3(seed=0, device=dev)
+    seqs = [r3d.Sequence.allocate(r3d.Context(w.params()), [(f.row_ptr, f.toa) for f in w.frames], dev)
+            for w in wls]
+    for q in seqs:
+        q.init_state()
+    batch = r3d.Batch(seqs, blocks=0)
+    batch.launch()
+    assert batch.status() == 0
+    batch.close()
+    wg = synth.config5(seed=0, device=dev)
+    frames = r3d.Frames([(f.row_ptr, f.toa) for f in wg.frames])
+    ctx = r3d.Context(wg.params())
+    N, P, E = len(wg.frames), wg.P, 5
+    init = r3d.State.empty(P, dev)
+    ctx.state_init(init)
+    ws = torch.empty(ctx.grad_workspace_size(N, E), dtype=torch.uint8, device=dev)
+    mean = torch.empty(N * P, device=dev)
+    var = torch.empty(N * P, device=dev)
+    grad = torch.empty(11 + wg.W, dtype=torch.float64, device=dev)
+    ctx.filter_forward(frames, E, init, mean, var, ws)
+    gm = (2.0 / (N * P)) * (mean - wg.depth_true.reshape(-1).float())
+    ctx.filter_backward(frames, E, gm, None, ws, grad)
+    torch.cuda.synchronize()
+    assert ctx.last_device_status() == 0
+    print("counter probe done", flush=True)
+
+
+COUNTER_KERNELS = {"k_tile_step<2,3>": "r3d::k_tile_step<2, 3>", "k_tile_step<0,3>": "r3d::k_tile_step<0, 3>",
+                   "k_step_plain": "r3d::k_step_plain<false>", "k_batch": "r3d::k_batch(",
+                   "k_adjoint": "k_adjoint(r3d::DevModel"}
+
+
+def record_counters(pmc_dirs, command: str, out_path: str = ""):
+    """Write profiles/counters_valu_lds.json from rocprofv3 --pmc runs (each
+    with --kernel-trace) of ``--counter-probe``, one directory per counter
+    pass: per kernel, the mean per launch of each counter and of the traced
+    duration. ``valu_busy_frac`` is rocprofv3's VALUBusy (the share of the
+    GPU's active cycles in which the compute units' vector ALUs execute)."""
+    import csv
+    import glob
+    out = {}
+    for pmc_dir in pmc_dirs:
+        cc = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)
+        kt = glob.glob(os.path.join(pmc_dir, "**", "*kernel_trace.csv"), recursive=True)
+        if not cc or not kt:
+            raise SystemExit(f"no counter_collection / kernel_trace CSV under {pmc_dir}")
+        dur = {}
+        for r in csv.DictReader(open(kt[0])):
+            dur[r["Correlation_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        per = {}
+        for r in csv.DictReader(open(cc[0])):
+            key = next((k for k, v in COUNTER_KERNELS.items() if v in r["Kernel_Name"]), None)
+            if key is None:
+                continue
+            d = per.setdefault(key, {"launches": {}, "counters": {}})
+            d["launches"][r["Correlation_Id"]] = dur.get(r["Correlation_Id"])
+            d["counters"].setdefault(r["Counter_Name"], {})
+            d["counters"][r["Counter_Name"]][r["Correlation_Id"]] = (
+                d["counters"][r["Counter_Name"]].get(r["Correlation_Id"], 0.0) + float(r["Counter_Value"]))
+        for key, d in per.items():
+            ids = [i for i, t in d["launches"].items() if t is not None]
+            if not ids:
+                continue
+            rec = out.setdefault(key, {})
+            rec.setdefault("launches", len(ids))
+            rec.setdefault("duration_us", round(sum(d["launches"][i] for i in ids) / len(ids), 2))
+            for name, vals in sorted(d["counters"].items()):
+                rec[name] = round(sum(vals.get(i, 0.0) for i in ids) / len(ids), 4)
+            if "VALUBusy" in rec:
+                rec["valu_busy_frac"] = round(rec["VALUBusy"] / 100.0, 4)
+    rec = {"kernel_src_sha": sources_sha(COUNTER_SRCS), "command": command, "kernels": out}
+    json.dump(rec, open(out_path or COUNTER_FILE, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def record_traffic(fetch_dir: str, write_dir: str, command: str, out_path: str = ""):
+    """Write the HBM traffic record of the split-fp16 tile step from two
+    rocprofv3 --pmc runs of --traffic-probe (FETCH_SIZE, then WRITE_SIZE):
+    each counter is scaled by what it reads for the probe's elementwise
+    kernel over 512 MiB (which reads and writes 524288 KiB)."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection CSV under {d}")
+        tile, calib = {}, {}
+        for r in csv.DictReader(open(f[0])):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if "r3d::k_tile_step<2, 3>" in r["Kernel_Name"]:
+                tile[int(r["Correlation_Id"])] = tile.get(int(r["Correlation_Id"]), 0.0) + v
+            elif "neg" in r["Kernel_Name"]:  # torch.neg over 512 MiB
+                calib[int(r["Correlation_Id"])] = calib.get(int(r["Correlation_Id"]), 0.0) + v
+        if len(tile) != 4 or len(calib) != 1:
+            raise SystemExit(f"{counter}: {len(tile)} tile launches, {len(calib)} calibration kernels")
+        return [tile[k] for k in sorted(tile)], next(iter(calib.values()))
+
+    fetch, fcal = per_dispatch(fetch_dir, "FETCH_SIZE")
+    write, wcal = per_dispatch(write_dir, "WRITE_SIZE")
+    fs, ws = 524288.0 / fcal, 524288.0 / wcal
+    byts = [1024.0 * (f * fs + w * ws) for f, w in zip(fetch, write)]
+    steady = (byts[2] + byts[3]) / 2
+    rec = {"kernel": "k_tile_step<2,3> (split fp16 matrix cores, W=64)",
+           "workload": "hist 256x256 T=4096 fp16, sequence call, one launch per frame",
+           "kernel_src_sha": sources_sha(KERNEL_SRCS), "command": command,
+           "fetch_kib": [round(x, 1) for x in fetch], "write_kib": [round(x, 1) for x in write],
+           "fetch_calibration_kib": round(fcal, 1), "write_calibration_kib": round(wcal, 1),
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+           "frame0_launch_bytes": round(byts[0]), "frame1_launch_bytes": round(byts[1]),
+           "steady_launch_bytes": round(steady),
+           "avg_bytes_per_launch_30": round((byts[0] + byts[1] + 28 * steady) / 30)}
+    json.dump(rec, open(out_path or TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def summarize_trace(path: str, steps: int, warmup: int, frames: int = 30):
+    """Per-launch figures of the split-fp16 tile step from a rocprofv3
+    kernel-trace CSV of the default command: the first ``warmup`` sequences
+    of ``frames`` launches are warm-up, the next ``steps`` are the timed
+    ones. Prints the mean kernel duration, the mean launch-to-launch period
+    inside the timed sequences and a per-frame table."""
+    import csv
+    rows = [r for r in csv.DictReader(open(path)) if r["Kernel_Name"].startswith("void r3d::k_tile_step<2, 3>")]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    t = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows]
+    timed = t[warmup * frames:(warmup + steps) * frames]
+    if len(timed) != steps * frames:
+        raise SystemExit(f"{len(t)} launches in the trace, expected at least {(warmup + steps) * frames}")
+    dur = [(e - b) / 1e3 for b, e in timed]
+    per = []
+    for s in range(steps):
+        seq = timed[s * frames:(s + 1) * frames]
+        per += [(seq[i + 1][0] - seq[i][0]) / 1e3 for i in range(frames - 1)]
+    bytes_launch = algorithmic_bytes_per_pixel_frame(4096) * 65536
+    md = sum(dur) / len(dur)
+    mp = sum(per) / len(per)
+    print(f"launches in trace {len(t)}; timed {len(timed)} ({steps} sequences of {frames})")
+    print(f"mean kernel duration {md:.2f} us -> {bytes_launch / md / 1e3:.1f} GB/s, "
+          f"frac {bytes_launch / md / 1e3 / HBM_PEAK_GBS:.4f}")
+    print(f"mean launch-to-launch period {mp:.2f} us -> {bytes_launch / mp / 1e3:.1f} GB/s, "
+          f"frac {bytes_launch / mp / 1e3 / HBM_PEAK_GBS:.4f}")
+    print("frame | duration mean / min / max (us)")
+    for f in range(frames):
+        d = [dur[s * frames + f] for s in range(steps)]
+        print(f"{f:5d} | {sum(d) / len(d):7.1f} {min(d):7.1f} {max(d):7.1f}")
 
 
 def traffic_probe():
@@ -169,7 +370,8 @@ def run_gpu(args):
         tf = flop / (pl * 1e-3) / 1e12
         plain = dict(value=P * F * args.steps / pw, ms_per_step=1e3 * pw / args.steps,
                      launch_ms=pl, precision="fp32", entry="r3d_run_hist (one launch per frame)",
-                     tflops=tf, valu_frac=tf / FP32_VALU_PEAK_TFLOPS)
+                     tflops=tf, valu_frac=tf / FP32_VALU_PEAK_TFLOPS,
+                     counters=recorded_counters("k_tile_step<0,3>"))
     # algorithmic bytes of one frame per launch
     bytes_launch = algorithmic_bytes_per_pixel_frame(T) * P
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
@@ -177,6 +379,7 @@ def run_gpu(args):
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=measured_traffic(args.precision, F),
                 kernel=f"k_tile_step (one launch per frame, {F}-frame sequence call)",
+                counters=recorded_counters("k_tile_step<2,3>"),
                 launch_ms=round(launch_ms, 5), bytes_per_launch=round(bytes_launch))
     # what the accuracy check of the timed run needs: frame F-1's histograms,
     # its input state (the sequence call leaves it in the second buffer) and
@@ -187,6 +390,44 @@ def run_gpu(args):
     res = dict(value=value, ms_per_step=ms_per_step, plain=plain, roofline=roof, P=P, F=F, T=T,
                params=params, tail=tail)
     return res
+
+
+def run_video(args):
+    """Photon-list video: 128x128 x 50 frames, T=1500, CSR int16 ToAs
+    (signal Poisson(3), background Poisson(30)), fp32 per-pixel step
+    (r3d_step_csr, one launch per frame), inputs resident on the device;
+    median over the repetitions of one pass over the 50 frames."""
+    import torch
+    import synth
+    from paper_2004_09211_amd import r3d
+
+    dev = torch.device("cuda:0")
+    wl = synth.config2(seed=0, device=dev)
+    ctx = r3d.Context(wl.params())
+    st = [r3d.State.empty(wl.P, dev), r3d.State.empty(wl.P, dev)]
+    out = r3d.Outputs.empty(wl.P, dev)
+    frames = [(f.row_ptr, f.toa) for f in wl.frames]
+    N = len(frames)
+    times = []
+    for i in range(args.video_reps + 1):
+        ctx.state_init(st[0])
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for n in range(N):
+            ctx.step_csr(*frames[n], st[n % 2], st[(n + 1) % 2], out)
+        e1.record()
+        torch.cuda.synchronize()
+        if i > 0:
+            times.append(e0.elapsed_time(e1))
+    if ctx.last_device_status() != 0:
+        raise RuntimeError("video pass reported a device error")
+    ms = sorted(times)[len(times) // 2]
+    photons = sum(int(f.row_ptr[-1]) for f in wl.frames)
+    return dict(value=round(wl.P * N / (ms * 1e-3), 1), unit="pixel-frames/s", ms_per_pass=round(ms, 3),
+                ms_per_frame=round(ms / N, 4), photons_per_frame=round(photons / N),
+                valu=recorded_counters("k_step_plain"),
+                workload="128x128 x 50 frames, T=1500, photon lists (CSR int16), fp32 per-pixel step")
 
 
 def run_batched(args):
@@ -251,6 +492,7 @@ def run_batched(args):
             raise RuntimeError("per-frame path reported a device error")
     photons = sum(int(f.row_ptr[-1]) for w in wls for f in w.frames)
     return dict(value=round(pf / (ms * 1e-3), 1), unit="pixel-frames/s", ms_per_pass=round(ms, 3),
+                valu=recorded_counters("k_batch"),
                 pixel_frames=pf, photons=photons,
                 per_frame_launches=dict(value=round(pf / (pms[0] * 1e-3), 1),
                                         ms_per_pass=round(pms[0], 3)),
@@ -298,6 +540,7 @@ def run_grad(args):
         raise RuntimeError("gradient pass reported a device error")
     fms, bms = sorted(fw)[len(fw) // 2], sorted(bw)[len(bw) // 2]
     return dict(value=round(N * P / ((fms + bms) * 1e-3), 1), unit="pixel-frames/s",
+                valu=recorded_counters("k_adjoint"),
                 forward_ms=round(fms, 3), backward_ms=round(bms, 3),
                 backward_over_forward=round(bms / fms, 2), ckpt_every=E,
                 workload="128x128 x 20 frames, T=1024, photon lists; gradient w.r.t. beta, "
@@ -437,6 +680,20 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--grad-reps", type=int, default=5)
     ap.add_argument("--traffic-probe", action="store_true")
+    ap.add_argument("--counter-probe", action="store_true")
+    ap.add_argument("--summarize-trace", default="",
+                    help="kernel-trace CSV of a rocprofv3 run of this script: print the tile "
+                         "step's per-launch figures over the timed sequences and exit")
+    ap.add_argument("--record-counters", nargs="*", default=None,
+                    help="output directory of a rocprofv3 --pmc --kernel-trace run of "
+                         "--counter-probe: write the counter record under profiles/ and exit")
+    ap.add_argument("--record-command", default="")
+    ap.add_argument("--record-out", default="", help="where the record goes (default: under profiles/)")
+    ap.add_argument("--record-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="output directories of the two rocprofv3 --pmc runs of --traffic-probe "
+                         "(FETCH_SIZE, WRITE_SIZE): write the traffic record and exit")
+    ap.add_argument("--no-video", action="store_true")
+    ap.add_argument("--video-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is measured on a single MI355X "
@@ -446,8 +703,20 @@ def main():
     # the oracle's workers are single-threaded processes
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[k] = "1"
+    if args.record_traffic:
+        record_traffic(*args.record_traffic, args.record_command, args.record_out)
+        return
+    if args.record_counters is not None:
+        record_counters(args.record_counters, args.record_command, args.record_out)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.steps, args.warmup, args.frames)
+        return
     if args.traffic_probe:
         traffic_probe()
+        return
+    if args.counter_probe:
+        counter_probe()
         return
     leg = cpu = accuracy = None
     if not args.no_cpu_baseline:
@@ -460,6 +729,7 @@ def main():
         accuracy = leg.accuracy(res["params"], res["tail"], args.accuracy_pixels)
         leg.close()
     res.pop("tail")
+    video = None if args.no_video else run_video(args)
     batched = None if args.no_batched else run_batched(args)
     gradient = None if args.no_grad else run_grad(args)
     line = dict(
@@ -479,9 +749,10 @@ def main():
                          entry=res["plain"]["entry"],
                          tflops=round(res["plain"]["tflops"], 2),
                          valu_frac=round(res["plain"]["valu_frac"], 4),
+                         counters=res["plain"]["counters"],
                          speedup=round(res["value"] / res["plain"]["value"], 3))),
-        roofline=res["roofline"], accuracy=accuracy, cpu_baseline=cpu, batched=batched,
-        gradient=gradient)
+        roofline=res["roofline"], accuracy=accuracy, cpu_baseline=cpu, video=video,
+        batched=batched, gradient=gradient)
     print(json.dumps(line), flush=True)
 
 

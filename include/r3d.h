@@ -355,7 +355,9 @@ r3d_status r3d_filter_forward(r3d_ctx *ctx, const r3d_frames *frames, int32_t ck
  * ckpt_every and workspace. grad_mean: device float[nframes*P] = dJ/dmean;
  * grad_var: the same for var, or NULL (zero). grad: device double[11 + W],
  * overwritten with dJ/dbeta, dJ/dsigma_rw2, dJ/dnu[0..8], dJ/dirf[0..W-1]
- * (the tap gradient is 0 for a zero tap). */
+ * (the tap gradient is 0 for a zero tap; at a zero weight nu_k the nu_k
+ * entry is the one-sided derivative, the component's unweighted density
+ * over the prior summed against the posterior adjoint). */
 r3d_status r3d_filter_backward(r3d_ctx *ctx, const r3d_frames *frames, int32_t ckpt_every,
                                const float *grad_mean, const float *grad_var,
                                void *workspace, size_t workspace_bytes, double *grad,

@@ -14,7 +14,9 @@
 //   dJ/dirf_j += s beta irf_j^(beta-1) sum_d g(d) z[d-c+j]
 //   dJ/dm_k    = sum_d g r_k (d-m_k) / V_k
 //   dJ/dV_k    = sum_d g r_k ((d-m_k)^2 - V_k) / (2 V_k^2)   (-> sigma_rw2 and v_k)
-//   dJ/dnu_k  += sum_d g r_k / nu_k.
+//   dJ/dnu_k  += sum_d g r_k / nu_k = sum_d g exp(q_k - log nu_k - log f),
+// the last form also for a zero weight, where it is the one-sided derivative
+// (the component's unweighted density over f).
 // One wavefront per pixel, on the candidate depths of the forward step
 // (depths outside carry exactly zero weight in fp32): the frame's mean,
 // variance and log2 normaliser come from the forward step; pass 2 forms
@@ -117,6 +119,15 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
 #pragma unroll
   for (int k = 0; k < 9; ++k) a0[k] = a1[k] = a2[k] = 0.f;
   float ab = 0.f;
+  // zero-weight components (wave-uniform): their unweighted log2 density
+  // q_k - log2 nu_k, for the one-sided derivative in nu_k
+  const unsigned zw = ~live & 0x1ffu;
+  float an[9], wz[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    an[k] = 0.f;
+    wz[k] = (zw >> k & 1u) ? -0.5f * (kLog2TwoPi + fast_log2(Vk[k])) : 0.f;
+  }
   for (int d0 = dlo_c; d0 <= dhi_c; d0 += 64) {
     unsigned cand, cmask;
     chunk_masks(C, R, Rl, d0, cand, cmask);
@@ -157,6 +168,7 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
       a0[k] += t;
       a1[k] = fmaf(t, e, a1[k]);
       a2[k] = fmaf(t * e, e, a2[k]);
+      if (zw >> k & 1u) an[k] = fmaf(gr, fast_exp2(wz[k] - e * e * C.k2[k] - mx), an[k]);
     }
   }
   wave_fence();
@@ -196,6 +208,8 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
       vbar = (s2 / V - s0) / (2.f * V);
       sig_bar += vbar;
       accT[2 + k] += s0 / M.nu[k];
+    } else if (zw >> k & 1u) {
+      accT[2 + k] += group_sum<1, 32>(an[k]);
     }
     if (lane == 0) {
       const bool own = (nb >> k) & 1u;
