@@ -611,7 +611,8 @@ class OracleLeg:
         dt = time.perf_counter() - t0
         n = wl.P * frames
         return dict(value=round(n / dt, 2), unit="pixel-frames/s", cores=self.workers,
-                    kind="oracle",
+                    kind="oracle", host_cpus=os.cpu_count(),
+                    host_cpus_usable=len(os.sched_getaffinity(0)),
                     sample=f"{rows}x{rows} crop x {frames} frames of the same workload recipe "
                            f"(T=4096, drawn on the host; {n} pixel-frames, {dt:.1f} s on "
                            f"{self.workers} single-threaded worker processes)")

@@ -13,5 +13,5 @@ from .r3d_oracle import (  # noqa: F401
     cost_from_histogram_pirf, cost_from_photons, flat_component, prior_components, log_prior,
     posterior_moments, background_intensity, pi0_next, init_state, step, run,
     gaussian_irf_sigma, filter_loss, filter_loss_grad_fd, argmax_with_margin,
-    min_divergence, msl_objective, msl_min_divergence,
+    min_divergence, msl_objective, msl_min_divergence, gauss_cost, gauss_min_divergence,
 )

@@ -523,6 +523,70 @@ def msl_min_divergence(z_bands, models) -> dict:
 
 
 # ---------------------------------------------------------------------------
+# continuous ToAs, Gaussian IRF: the minimum-divergence depth off the grid
+# (Sec. II-B, eq. beta_div2 with the photon sum; Sec. V: the correlation may
+# be continuous, and a Gaussian IRF simplifies the update rules)
+# ---------------------------------------------------------------------------
+def gauss_cost(y: np.ndarray, d, sigma: float, beta: float) -> np.ndarray:
+    """(beta+1)/beta * sum_k f0(y_k | d)^beta for a Gaussian IRF of standard
+    deviation sigma (unit integral) and continuous depth(s) d: the photon sum
+    of eq. beta_div2 without the constant. With f0(y|d) = N(y; d, sigma^2),
+    f0^beta = (2 pi sigma^2)^(-beta/2) exp(-beta (y - d)^2 / (2 sigma^2))."""
+    y = np.asarray(y, dtype=np.float64)
+    d = np.atleast_1d(np.asarray(d, dtype=np.float64))
+    amp = (2.0 * math.pi * sigma * sigma) ** (-beta / 2.0)
+    e = y[None, :] - d[:, None]
+    return (beta + 1.0) / beta * amp * np.exp(-beta * e * e / (2.0 * sigma * sigma)).sum(axis=1)
+
+
+def gauss_min_divergence(row_ptr, toa, sigma: float, beta: float, d_lo: int, D: int,
+                         tol: float = 1e-12, max_iter: int = 10000) -> dict:
+    """Minimum beta-divergence depth of each pixel for a Gaussian IRF,
+    maximised over continuous d. The photon ToAs are the bin indices (the
+    depth convention of the grid). The objective sum_k exp(-(y_k - d)^2 /
+    (2 h^2)), h^2 = sigma^2 / beta, is stationary where
+    d = sum_k w_k y_k / sum_k w_k, w_k = exp(-(y_k - d)^2 / (2 h^2)); this
+    fixed point, iterated from the first maximiser on the depth grid
+    (photon form, every photon), climbs to the local maximum of that
+    maximiser's basin, held to the grid's span [d_lo, d_lo + D - 1] (the
+    admissible depths). Returns the continuous depth, the cost there (natural
+    log units, gauss_cost), the grid maximiser and the grid margin (best grid
+    value minus the best value two or more bins away). A pixel without
+    photons keeps d_lo with cost 0."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    P = len(row_ptr) - 1
+    grid = d_lo + np.arange(D, dtype=np.float64)
+    depth = np.full(P, float(d_lo))
+    value = np.zeros(P)
+    gidx = np.zeros(P, dtype=np.int64)
+    margin = np.full(P, np.inf)
+    h2 = sigma * sigma / beta
+    for p in range(P):
+        y = np.asarray(toa[row_ptr[p]:row_ptr[p + 1]], dtype=np.float64)
+        if y.size == 0:
+            continue
+        J = gauss_cost(y, grid, sigma, beta)
+        i = int(np.argmax(J))
+        gidx[p] = i
+        far = np.abs(np.arange(D) - i) >= 2
+        if far.any():
+            margin[p] = J[i] - J[far].max()
+        d = grid[i]
+        for _ in range(max_iter):
+            w = np.exp(-(y - d) ** 2 / (2.0 * h2))
+            dn = float(np.dot(w, y) / w.sum())
+            if abs(dn - d) <= tol * max(1.0, abs(d)):
+                d = dn
+                break
+            d = dn
+        # the admissible depths are the grid's span: a basin whose peak lies
+        # beyond it rises to the nearer end of the span
+        depth[p] = d = min(max(d, grid[0]), grid[-1])
+        value[p] = gauss_cost(y, d, sigma, beta)[0]
+    return dict(depth=depth, value=value, grid_index=gidx, margin=margin)
+
+
+# ---------------------------------------------------------------------------
 # differentiable filter: loss and its finite-difference gradient
 # ---------------------------------------------------------------------------
 def gaussian_irf_sigma(sigma: float, W: int, c: int) -> np.ndarray:

@@ -318,3 +318,92 @@ def test_pixel_irf_reflectivity_matches_generic_optimiser():
                                 options=dict(ftol=1e-15, gtol=1e-12, maxiter=2000))
         assert r[p] == pytest.approx(res.x[0], rel=2e-4)
         assert z[p].sum() == pytest.approx(r[p] * s.sum() + b[p] * T, rel=1e-9)
+
+
+# ------------------------------- continuous depth, Gaussian IRF (Sec. II-B, V)
+def _csr(lists):
+    counts = [len(x) for x in lists]
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    toa = np.concatenate([np.asarray(x, dtype=np.int64) for x in lists]) if sum(counts) else np.zeros(0, np.int64)
+    return row_ptr, toa
+
+
+def test_gauss_cost_is_photon_form_with_sampled_gaussian_taps():
+    """On the grid, the Gaussian-IRF cost equals the photon form of the
+    discrete cost (cost_from_photons) with taps irf[j] = N(j - c; 0, sigma^2)
+    sampled from the density (wide enough that no photon leaves the taps)."""
+    sigma, beta, c = 2.3, 0.35, 30
+    W = 2 * c + 1
+    j = np.arange(W) - c
+    taps = np.exp(-j * j / (2 * sigma * sigma)) / np.sqrt(2 * np.pi * sigma * sigma)
+    m = make_model(rows=1, cols=3, T=80, W=W, c=c, beta=beta, irf=taps, d_lo=20, D=40)
+    row_ptr, toa = _csr([[31, 33, 47, 50], [45], [30, 30, 58]])
+    ref = oracle.cost_from_photons(row_ptr, toa, m)
+    for p in range(3):
+        y = toa[row_ptr[p]:row_ptr[p + 1]]
+        np.testing.assert_allclose(oracle.gauss_cost(y, m.grid, sigma, beta), ref[p], rtol=1e-13, atol=0)
+
+
+def test_gauss_min_divergence_closed_forms():
+    """One photon: the maximiser is the photon itself and the cost is
+    (beta+1)/beta (2 pi sigma^2)^(-beta/2). Two photons closer than 2h
+    (h = sigma / sqrt(beta)): the objective is unimodal and symmetric, so the
+    maximiser is their midpoint. No photon: d_lo, cost 0."""
+    sigma, beta = 3.0, 0.3
+    h = sigma / np.sqrt(beta)
+    row_ptr, toa = _csr([[40], [37, 45], [], [30, 30 + int(1.9 * h)]])
+    r = oracle.gauss_min_divergence(row_ptr, toa, sigma, beta, 10, 80)
+    assert r["depth"][0] == 40.0
+    assert r["value"][0] == pytest.approx((beta + 1) / beta * (2 * np.pi * sigma ** 2) ** (-beta / 2), rel=1e-14)
+    assert r["depth"][1] == pytest.approx(41.0, abs=1e-9)
+    assert r["depth"][2] == 10.0 and r["value"][2] == 0.0
+    assert r["depth"][3] == pytest.approx(30 + int(1.9 * h) / 2, abs=1e-9)
+
+
+def test_gauss_min_divergence_brute_force_and_stationarity():
+    """Random tiny pixels: where the grid margin is clear, the result is the
+    global maximiser of the continuous objective found by a dense search
+    (step 1e-4 over the grid's span, then a golden-section polish by scipy);
+    at every result the objective is stationary and concave."""
+    rng = np.random.default_rng(11)
+    sigma, beta, d_lo, D = 1.8, 0.45, 5, 50
+    lists = [list(rng.integers(0, 60, rng.integers(1, 9))) for _ in range(25)]
+    row_ptr, toa = _csr(lists)
+    r = oracle.gauss_min_divergence(row_ptr, toa, sigma, beta, d_lo, D)
+    fine = np.arange(d_lo, d_lo + D - 1 + 1e-9, 1e-4)
+    checked = 0
+    for p in range(25):
+        y = toa[row_ptr[p]:row_ptr[p + 1]].astype(float)
+        d = r["depth"][p]
+        # stationary and concave there (central differences), unless held
+        # at an end of the span, where the objective rises towards the end
+        e = 1e-4
+        f = lambda x: oracle.gauss_cost(y, x, sigma, beta)[0]
+        g1 = (f(d + e) - f(d - e)) / (2 * e)
+        g2 = (f(d + e) - 2 * f(d) + f(d - e)) / (e * e)
+        if d == d_lo:
+            assert g1 <= 0
+        elif d == d_lo + D - 1:
+            assert g1 >= 0
+        else:
+            assert abs(g1) <= 1e-7 * max(1.0, f(d)) and g2 < 0
+        if r["margin"][p] > 1e-3 * r["value"][p]:
+            J = oracle.gauss_cost(y, fine, sigma, beta)
+            x0 = fine[np.argmax(J)]
+            res = optimize.minimize_scalar(lambda x: -f(x), method="bounded", options=dict(xatol=1e-10),
+                                           bounds=(max(d_lo, x0 - 2e-4), min(d_lo + D - 1, x0 + 2e-4)))
+            assert d == pytest.approx(res.x, abs=1e-5)
+            assert r["value"][p] >= -res.fun - 1e-12 * abs(res.fun)
+            checked += 1
+    assert checked >= 15
+
+
+def test_gauss_min_divergence_shift_equivariance():
+    """Shifting every ToA by k bins shifts the continuous estimate by k."""
+    rng = np.random.default_rng(4)
+    lists = [list(rng.integers(20, 60, rng.integers(1, 12))) for _ in range(12)]
+    row_ptr, toa = _csr(lists)
+    a = oracle.gauss_min_divergence(row_ptr, toa, 2.5, 0.3, 0, 100)
+    b = oracle.gauss_min_divergence(row_ptr, toa + 17, 2.5, 0.3, 0, 100)
+    np.testing.assert_allclose(b["depth"], a["depth"] + 17, atol=1e-9)
+    np.testing.assert_allclose(b["value"], a["value"], rtol=1e-12)
