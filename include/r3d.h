@@ -215,6 +215,27 @@ r3d_status r3d_min_divergence_msl(r3d_ctx *const *bands, int32_t nbands,
                                   const uint16_t *const *hist, int32_t *argmax, float *value,
                                   void *stream);
 
+/* Continuous minimum-divergence depth of each pixel for a Gaussian IRF
+ * (Sec. II-B, eq. beta_div2 in its photon form with f0(y|d) = N(y; d,
+ * sigma^2) of unit integral; Sec. V: the correlation may be continuous and a
+ * Gaussian IRF simplifies the updates). The photon sum is, up to a constant
+ * factor, sum_k exp(-beta (y_k - d)^2 / (2 sigma^2)) with the ToAs y_k taken
+ * as bin indices; it is maximised over real d in [d_lo, d_lo + D - 1] by the
+ * stationarity fixed point d = sum w_k y_k / sum w_k started from the first
+ * grid maximiser (the local maximum of that maximiser's basin; a basin whose
+ * peak lies beyond the span ends at the span's end). Uses the context's
+ * rows, cols, T, d_lo, D and beta; its IRF is not used. row_ptr, toa: CSR
+ * photon lists as for r3d_step_csr. sigma: the IRF's standard deviation in
+ * bins, 0 < sigma <= T (else R3D_EINVAL). depth: device float [P]; value:
+ * device float [P] or NULL, (beta+1)/beta * sum_k f0(y_k|d)^beta at the
+ * depth (natural-log units); grid_argmax: device int32 [P] or NULL, the grid
+ * maximiser. A pixel without photons gets d_lo and 0. Evaluated in fp32
+ * (terms below 2^-40 of one photon's peak are dropped). Asynchronous; a ToA
+ * outside [0, T) sets R3D_ERANGE in the device error word. */
+r3d_status r3d_min_divergence_gauss(r3d_ctx *ctx, const int32_t *row_ptr, const int16_t *toa,
+                                    double sigma, float *depth, float *value,
+                                    int32_t *grid_argmax, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Pixel-dependent IRFs (Sec. II-A: the method applies when the shape of the
  * IRF depends on the pixel).

@@ -5,6 +5,8 @@
 // The fused step (pixel_step, r3d_pixel.hpp) keeps the pixel's histogram in
 // LDS, evaluates the cost and the prior only on candidate depths, and
 // reduces argmax and moments over the wavefront.
+#include <cmath>
+
 #include "r3d_device.hpp"
 #include "r3d_pixel.hpp"
 
@@ -258,6 +260,126 @@ hipError_t launch_step_pirf(const DevModel& M, const StepIO& io, bool from_hist,
     hipLaunchKernelGGL(k_step_pirf<true>, grid, dim3(64 * nw), lds, s, M, io, irf_pix, c_pix);
   else
     hipLaunchKernelGGL(k_step_pirf<false>, grid, dim3(64 * nw), lds, s, M, io, irf_pix, c_pix);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------- continuous depth, Gaussian IRF
+// Minimum-divergence depth off the grid for a Gaussian IRF of standard
+// deviation sigma (Sec. II-B, eq. beta_div2 in its photon form; Sec. V: the
+// correlation may be continuous, and a Gaussian IRF simplifies the updates).
+// With f0(y|d) = N(y; d, sigma^2) the photon sum is, up to the factor
+// (beta+1)/beta (2 pi sigma^2)^(-beta/2),
+//   J(d) = sum_t z_t exp2(-a (t - d)^2),  a = beta log2(e) / (2 sigma^2),
+// over the pixel's histogram (ToAs are bin indices). One wavefront per
+// pixel: the LDS histogram of its photon list, J on every grid depth (each
+// lane walks the non-empty bins within the truncation radius of its depths;
+// terms beyond it are below 2^-40 of one photon's peak) and the first grid
+// maximiser, then the stationarity fixed point d <- d + sum w (t - d) /
+// sum w (w = z_t exp2(-a (t - d)^2)) from it, lanes taking the window's
+// bins, until the step is below 1e-5 bins (at most 200 steps); the result is
+// held to the grid's span.
+constexpr float kGaussTail2 = 40.f;  // log2 units: truncation of the Gaussian terms
+
+__global__ void __launch_bounds__(256) k_gauss_mindiv(DevModel M, const int32_t* __restrict__ row_ptr,
+                                                      const int16_t* __restrict__ toa, float a, float amp,
+                                                      float* __restrict__ depth, float* __restrict__ value,
+                                                      int32_t* __restrict__ grid_argmax) {
+  extern __shared__ __align__(16) float smem_f[];
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned* hist = reinterpret_cast<unsigned*>(smem_f) + (size_t)wave * pixel_lds_words(M.T);
+  unsigned* nzmask = hist + ((M.T + 1) >> 1);
+  const int p = blockIdx.x * nw + wave;
+  if (p >= M.P) return;
+  {
+    uint4* z4 = reinterpret_cast<uint4*>(hist);
+    const int n4 = pixel_lds_words(M.T) >> 2;
+    for (int w = lane; w < n4; w += 64) z4[w] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  wave_fence();
+  unsigned bad = 0u;
+  const float K = csr_histogram(M, row_ptr, toa, p, lane, hist, nzmask, bad);
+  if (bad) atomicOr(M.err, bad);
+  wave_fence();
+  const int R = (int)ceilf(sqrtf(kGaussTail2 / a));  // truncation radius, bins
+  const int dhi = M.d_lo + M.D - 1;
+
+  // J on the grid: each lane its depths, in increasing bin order
+  float best = -INFINITY;
+  int bidx = 0x7fffffff;
+  if (K > 0.f) {
+    for (int i = lane; i < M.D; i += 64) {
+      const int d = M.d_lo + i;
+      const int lo = max(d - R, 0), hi = min(d + R, M.T - 1);
+      float J = 0.f;
+      for (int t = lo; t <= hi;) {
+        const int base = t & ~31;
+        unsigned bits = nzmask[base >> 5] & (~0u << (t - base));
+        if (hi - base < 31) bits &= (2u << (hi - base)) - 1u;
+        while (bits) {
+          const int tb = base + __builtin_ctz(bits);
+          bits &= bits - 1u;
+          const float e = (float)(tb - d);
+          J = fmaf(packed_count(hist, tb), fast_exp2(-a * e * e), J);
+        }
+        t = base + 32;
+      }
+      if (J > best) {
+        best = J;
+        bidx = i;
+      }
+    }
+  }
+  group_argmax<1, 32>(best, bidx);
+  if (bidx == 0x7fffffff) bidx = 0;
+
+  // the stationarity fixed point from the grid maximiser
+  float d = (float)(M.d_lo + bidx);
+  float S0 = 0.f;
+  auto sums = [&](float x, float& s0, float& s1) {
+    const int lo = max((int)floorf(x) - R, 0), hi = min((int)ceilf(x) + R, M.T - 1);
+    float a0 = 0.f, a1 = 0.f;
+    for (int t = lo + lane; t <= hi; t += 64) {
+      const float z = packed_count(hist, t);
+      if (z > 0.f) {
+        const float e = (float)t - x;
+        const float w = z * fast_exp2(-a * e * e);
+        a0 += w;
+        a1 = fmaf(w, e, a1);
+      }
+    }
+    s0 = group_sum<1, 32>(a0);
+    s1 = group_sum<1, 32>(a1);
+  };
+  if (K > 0.f) {
+    for (int it = 0; it < 200; ++it) {
+      float s1;
+      sums(d, S0, s1);
+      if (!(S0 > 0.f)) break;
+      const float step = s1 / S0;
+      d += step;
+      if (fabsf(step) <= 1e-5f) break;
+    }
+    d = fminf(fmaxf(d, (float)M.d_lo), (float)dhi);
+    float s1;
+    sums(d, S0, s1);
+  }
+  if (lane == 0) {
+    depth[p] = d;
+    if (value) value[p] = M.scale2 * kLn2 * amp * S0;
+    if (grid_argmax) grid_argmax[p] = M.d_lo + bidx;
+  }
+}
+
+hipError_t launch_gauss_mindiv(const DevModel& M, const int32_t* row_ptr, const int16_t* toa,
+                               double sigma, float* depth, float* value, int32_t* grid_argmax,
+                               hipStream_t s) {
+  const int nw = waves_for((size_t)pixel_lds_words(M.T) * 4, 0);
+  if (nw == 0) return hipErrorInvalidValue;
+  const float a = (float)(M.beta_d * 1.4426950408889634 / (2.0 * sigma * sigma));
+  const float amp = (float)std::pow(2.0 * 3.14159265358979323846 * sigma * sigma, -0.5 * M.beta_d);
+  const dim3 grid((M.P + nw - 1) / nw);
+  hipLaunchKernelGGL(k_gauss_mindiv, grid, dim3(64 * nw), (size_t)nw * pixel_lds_words(M.T) * 4, s,
+                     M, row_ptr, toa, a, amp, depth, value, grid_argmax);
   return hipGetLastError();
 }
 

@@ -366,6 +366,15 @@ r3d_status r3d_min_divergence(r3d_ctx* ctx, const uint16_t* hist, int32_t* argma
                                        (hipStream_t)stream));
 }
 
+r3d_status r3d_min_divergence_gauss(r3d_ctx* ctx, const int32_t* row_ptr, const int16_t* toa,
+                                    double sigma, float* depth, float* value, int32_t* grid_argmax,
+                                    void* stream) {
+  if (!ctx || !row_ptr || !toa || !depth) return R3D_EINVAL;
+  if (!(sigma > 0.0) || !(sigma <= (double)ctx->prm.T)) return R3D_EINVAL;
+  return hip_status(r3d::launch_gauss_mindiv(ctx->dm, row_ptr, toa, sigma, depth, value, grid_argmax,
+                                             (hipStream_t)stream));
+}
+
 r3d_status r3d_min_divergence_msl(r3d_ctx* const* bands, int32_t nbands,
                                   const uint16_t* const* hist, int32_t* argmax, float* value,
                                   void* stream) {

@@ -67,5 +67,10 @@ hipError_t launch_step_plain(const DevModel& m, const StepIO& io, bool from_hist
 hipError_t launch_step_pirf(const DevModel& m, const StepIO& io, bool from_hist,
                             const double* irf_pix, const int32_t* c_pix, hipStream_t s);
 bool plain_supported(const DevModel& m);
+// continuous minimum-divergence depth for a Gaussian IRF of standard
+// deviation sigma, from photon lists; value and grid_argmax may be null
+hipError_t launch_gauss_mindiv(const DevModel& m, const int32_t* row_ptr, const int16_t* toa,
+                               double sigma, float* depth, float* value, int32_t* grid_argmax,
+                               hipStream_t s);
 
 }  // namespace r3d

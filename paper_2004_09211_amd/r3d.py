@@ -87,6 +87,8 @@ SIGNATURES = {
     "r3d_filter_backward": (c_int32, [c_void_p, POINTER(CFrames), c_int32, c_void_p, c_void_p,
                                       c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),
     "r3d_min_divergence": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "r3d_min_divergence_gauss": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
+                                           c_void_p, c_void_p]),
     "r3d_min_divergence_msl": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_void_p,
                                          c_void_p, c_void_p]),
     "r3d_step_pirf": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -287,6 +289,25 @@ class Context:
                                        _ptr(value, torch.float32), _stream(stream)),
                "r3d_min_divergence")
         return argmax, value
+
+    def min_divergence_gauss(self, row_ptr, toa, sigma: float, depth=None, value=None,
+                             grid_argmax=None, stream=None):
+        """Continuous minimum-divergence depth of each pixel for a Gaussian
+        IRF of standard deviation ``sigma`` bins, from CSR photon lists;
+        returns (depth float [P], value float [P], grid_argmax int32 [P])."""
+        dev = row_ptr.device
+        if depth is None:
+            depth = torch.empty(self.P, dtype=torch.float32, device=dev)
+        if value is None:
+            value = torch.empty(self.P, dtype=torch.float32, device=dev)
+        if grid_argmax is None:
+            grid_argmax = torch.empty(self.P, dtype=torch.int32, device=dev)
+        _check(_lib.r3d_min_divergence_gauss(self._h, _ptr(row_ptr, torch.int32), _ptr(toa, torch.int16),
+                                             float(sigma), _ptr(depth, torch.float32),
+                                             _ptr(value, torch.float32), _ptr(grid_argmax, torch.int32),
+                                             _stream(stream)),
+               "r3d_min_divergence_gauss")
+        return depth, value, grid_argmax
 
     def step_pirf(self, frame, irf_pix, prev: State, nxt: State, out: Outputs, c_pix=None,
                   pi_in=None, faulty=None, stream=None):

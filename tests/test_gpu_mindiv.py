@@ -363,3 +363,101 @@ def test_step_pirf_argument_errors(lib):
         ctx.step_pirf((fr.row_ptr.to(DEV), fr.toa.to(DEV)), torch.as_tensor(irf_pix, device=DEV),
                       st, st, out)
     assert e.value.status == -1
+
+
+# ------------------------------- continuous depth, Gaussian IRF (Sec. II-B, V)
+def _gauss_check(wl, sigma, depth, value, gidx, label, pixels=None):
+    """GPU continuous estimates against the oracle (fp64). Where the
+    oracle's grid margin exceeds 1e-4 of its value the basin is unambiguous:
+    depth within 1e-3 bins plus an fp32 ulp, value within 1e-5 relative,
+    grid maximiser identical. Elsewhere the GPU's depth must be as good:
+    the objective there within 1e-5 relative of the oracle's maximum."""
+    rp = wl.frames[0].row_ptr.numpy()
+    toa = wl.frames[0].toa.numpy()
+    r = oracle.gauss_min_divergence(rp, toa, sigma, wl.beta, wl.d_lo, wl.D)
+    P = len(rp) - 1
+    pix = np.arange(P) if pixels is None else np.asarray(pixels)
+    d = depth.astype(np.float64)
+    sure = r["margin"] > 1e-4 * r["value"]
+    n_sure = 0
+    for p in pix:
+        y = toa[rp[p]:rp[p + 1]]
+        if sure[p]:
+            n_sure += 1
+            tol = 1e-3 + float(np.spacing(np.float32(abs(r["depth"][p]) + 1)))
+            assert abs(d[p] - r["depth"][p]) <= tol, (label, p, d[p], r["depth"][p])
+            assert value[p] == pytest.approx(r["value"][p], rel=1e-5, abs=1e-30), (label, p)
+            assert gidx[p] == wl.d_lo + r["grid_index"][p], (label, p)
+        else:
+            at = oracle.gauss_cost(y, d[p], sigma, wl.beta)[0] if len(y) else 0.0
+            assert at >= r["value"][p] * (1 - 1e-5), (label, p, at, r["value"][p])
+    return n_sure
+
+
+@pytest.mark.parametrize("shape", ["video_crop", "offset_grid"])
+def test_min_divergence_gauss_matches_oracle(lib, shape):
+    if shape == "video_crop":
+        wl = synth.config2(rows=8, cols=12, frames=1)
+        sigma = 3.0
+    else:
+        wl = synth.tiny_workload(rows=5, cols=9, T=200, W=9, c=4, frames=1, sigma=2.0, n_sig=12, n_bg=6)
+        wl.d_lo, wl.D, wl.d_min, wl.d_max = 13, 150, 13.0, 162.0
+        sigma = 2.0
+    ctx = lib.Context(wl.params())
+    f = wl.frames[0]
+    depth, value, gidx = ctx.min_divergence_gauss(f.row_ptr.to(DEV), f.toa.to(DEV), sigma)
+    assert ctx.last_device_status() == 0
+    n = _gauss_check(wl, sigma, depth.cpu().numpy(), value.cpu().numpy(), gidx.cpu().numpy(), shape)
+    assert n >= 0.8 * wl.P
+
+
+def test_min_divergence_gauss_edge_cases(lib):
+    """A pixel without photons gets d_lo and 0; one photon gives its bin; a
+    ToA outside [0, T) is reported; sigma must be positive."""
+    wl = synth.tiny_workload(rows=1, cols=4, T=64, W=9, c=4, frames=1)
+    ctx = lib.Context(wl.params())
+    rp = torch.tensor([0, 0, 1, 3, 5], dtype=torch.int32, device=DEV)
+    toa = torch.tensor([40, 10, 20, 63, 0], dtype=torch.int16, device=DEV)
+    depth, value, gidx = ctx.min_divergence_gauss(rp, toa, 1.5)
+    assert ctx.last_device_status() == 0
+    d = depth.cpu().numpy()
+    assert d[0] == wl.d_lo and float(value[0]) == 0.0
+    assert d[1] == 40.0 and int(gidx[1]) == 40
+    r = oracle.gauss_min_divergence(rp.cpu().numpy(), toa.cpu().numpy(), 1.5, wl.beta, wl.d_lo, wl.D)
+    np.testing.assert_allclose(d, r["depth"], atol=1e-3)
+    np.testing.assert_allclose(value.cpu().numpy(), r["value"], rtol=1e-5)
+    bad = torch.tensor([0, 1, 1, 1, 1], dtype=torch.int32, device=DEV)
+    ctx.min_divergence_gauss(bad, torch.tensor([64], dtype=torch.int16, device=DEV), 1.5)
+    assert ctx.last_device_status() == -2  # R3D_ERANGE
+    with pytest.raises(lib.R3DError):
+        ctx.min_divergence_gauss(rp, toa, 0.0)
+    with pytest.raises(lib.R3DError):
+        ctx.min_divergence_gauss(rp, toa, float("nan"))
+
+
+def test_min_divergence_gauss_full_video_frame_sampled(lib):
+    """The 128x128 video's first frame (T=1500, sigma=3): 300 sampled pixels
+    against the oracle."""
+    wl = synth.config2(frames=1)
+    ctx = lib.Context(wl.params())
+    f = wl.frames[0]
+    depth, value, gidx = ctx.min_divergence_gauss(f.row_ptr.to(DEV), f.toa.to(DEV), 3.0)
+    assert ctx.last_device_status() == 0
+    rng = np.random.default_rng(3)
+    pix = np.unique(np.concatenate([[0, 127, wl.P - 128, wl.P - 1], rng.choice(wl.P, 296, replace=False)]))
+    sub_rp = [0]
+    sub_toa = []
+    rp, toa = f.row_ptr.numpy(), f.toa.numpy()
+    for p in pix:
+        sub_toa.append(toa[rp[p]:rp[p + 1]])
+        sub_rp.append(sub_rp[-1] + rp[p + 1] - rp[p])
+    r = oracle.gauss_min_divergence(np.array(sub_rp), np.concatenate(sub_toa), 3.0, wl.beta, wl.d_lo, wl.D)
+    d = depth.cpu().numpy()[pix].astype(np.float64)
+    v = value.cpu().numpy()[pix]
+    sure = r["margin"] > 1e-4 * r["value"]
+    assert sure.sum() >= 250
+    np.testing.assert_allclose(d[sure], r["depth"][sure], atol=1e-3 + 2.5e-4)
+    np.testing.assert_allclose(v[sure], r["value"][sure], rtol=1e-5)
+    for i in np.flatnonzero(~sure):
+        y = np.concatenate(sub_toa)[sub_rp[i]:sub_rp[i + 1]]
+        assert oracle.gauss_cost(y, d[i], 3.0, wl.beta)[0] >= r["value"][i] * (1 - 1e-5)
