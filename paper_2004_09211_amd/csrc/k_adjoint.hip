@@ -119,15 +119,6 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
 #pragma unroll
   for (int k = 0; k < 9; ++k) a0[k] = a1[k] = a2[k] = 0.f;
   float ab = 0.f;
-  // zero-weight components (wave-uniform): their unweighted log2 density
-  // q_k - log2 nu_k, for the one-sided derivative in nu_k
-  const unsigned zw = ~live & 0x1ffu;
-  float an[9], wz[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    an[k] = 0.f;
-    wz[k] = (zw >> k & 1u) ? -0.5f * (kLog2TwoPi + fast_log2(Vk[k])) : 0.f;
-  }
   for (int d0 = dlo_c; d0 <= dhi_c; d0 += 64) {
     unsigned cand, cmask;
     chunk_masks(C, R, Rl, d0, cand, cmask);
@@ -168,10 +159,11 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
       a0[k] += t;
       a1[k] = fmaf(t, e, a1[k]);
       a2[k] = fmaf(t * e, e, a2[k]);
-      if (zw >> k & 1u) an[k] = fmaf(gr, fast_exp2(wz[k] - e * e * C.k2[k] - mx), an[k]);
     }
   }
   wave_fence();
+
+
 
   // ---- pass 3: tap sums G_j = sum_d g(d) z[d - c + j] over non-empty bins ----
   if (!faulty && dlo_c <= dhi_c) {
@@ -208,8 +200,6 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
       vbar = (s2 / V - s0) / (2.f * V);
       sig_bar += vbar;
       accT[2 + k] += s0 / M.nu[k];
-    } else if (zw >> k & 1u) {
-      accT[2 + k] += group_sum<1, 32>(an[k]);
     }
     if (lane == 0) {
       const bool own = (nb >> k) & 1u;
@@ -219,6 +209,44 @@ __device__ __forceinline__ void adjoint_pixel(const DevModel& M, const AdjIO& io
   }
   accT[0] += ab;
   accT[1] += sig_bar;
+
+  // ---- pass 4, zero-weight components only (wave-uniform): the one-sided
+  // derivative in nu_k, sum_d g(d) exp2(q_k - log2 nu_k - log2 f) with
+  // q_k - log2 nu_k the component's unweighted log2 density ----
+  const unsigned zw = ~live & 0x1ffu;
+  if (zw) {
+    float an[9], wz[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) an[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)  // log2 V = log2(log2(e) / 2) - log2 k2
+      wz[k] = (zw >> k & 1u) ? -0.5f * (kLog2TwoPi + fast_log2(0.5f * kLog2e) - fast_log2(C.k2[k])) : 0.f;
+    for (int d = dlo_c + lane; d <= dhi_c; d += 64) {
+      const float g = gbuf[d - dlo_c];
+      if (g == 0.f) continue;
+      float q[9];
+      float mx = -INFINITY;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const float e = (float)d - C.m[k];
+        q[k] = C.w2[k] - e * e * C.k2[k];
+        if (live & (1u << k)) mx = fmaxf(mx, q[k]);
+      }
+      float ssum = 0.f;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) ssum += (live & (1u << k)) ? fast_exp2(q[k] - mx) : 0.f;
+      const float gr = g * fast_rcp(ssum);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        if (!(zw >> k & 1u)) continue;
+        const float e = (float)d - C.m[k];
+        an[k] = fmaf(gr, fast_exp2(wz[k] - e * e * C.k2[k] - mx), an[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      if (zw >> k & 1u) accT[2 + k] += group_sum<1, 32>(an[k]);
+  }
 }
 
 // 4 wavefronts per SIMD (128 VGPRs, a few spills): the pixel passes are
