@@ -1,6 +1,8 @@
-"""Parity of the benchmark's configuration at full size: 256x256 pixels,
-T = 4096 fp16 histograms, 30 frames of the moving scene, the split fp16
-matrix-core engine (and the fp32 vector engine on three frames).
+"""Parity at full size, state-forced: the benchmark's configuration (256x256
+pixels, T = 4096 fp16 histograms, 30 frames of the moving scene, the split
+fp16 matrix-core engine, and the fp32 vector engine on three frames) and the
+128x128 x 50-frame photon-list video (plain, and with presence
+probabilities and faulty pixels).
 
 The GPU runs its own chain over all 30 frames (one step call per frame).
 At frames 0, 1, 2, 10, 20, 28 and 29 the GPU's input state (fp32, cast to
@@ -109,3 +111,57 @@ def test_full_size_state_forced(lib, workload, prec, frames):
         rep = compare(sub, ref, model=model, state=s_in, z=z, pixels=pix, mean_rel=1e-4,
                       var_rel=1e-3, int_rel=1e-3, label=f"{prec} frame {n}")
         print(prec, n, len(pix), rep, flush=True)
+
+
+# ------------------------------------------- the photon-list video, full size
+VIDEO_FRAMES = (0, 1, 2, 25, 49)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("case,frames", [("plain", VIDEO_FRAMES), ("faulty_pi", (1, 25, 49))])
+def test_full_size_video_state_forced(lib, case, frames):
+    """The 128x128 x 50-frame photon-list video (T = 1500, CSR int16, fp32
+    per-pixel step) at full size, state-forced as above: the GPU runs its own
+    chain over all 50 frames; at the listed frames about 290 sampled pixels
+    (corners, edges, the two 4x4 blocks with the most depth steps, random)
+    are stepped by the oracle from the GPU's input state. In the faulty_pi
+    case every frame has caller-supplied presence probabilities (uniform on
+    [0, 1]: about half the pixels undetected) and 5 % of the pixels are
+    faulty (their posterior is the prior alone, Sec. III-B)."""
+    wl = synth.config2()
+    model = oracle.Model.from_params(wl.params())
+    keep = set(frames)
+    pi_in = faulty = None
+    if case == "faulty_pi":
+        g0 = torch.Generator().manual_seed(31)
+        pi_in = [torch.rand(wl.P, generator=g0) for _ in range(wl.nframes)]
+        faulty = torch.rand(wl.P, generator=g0) < 0.05
+    ctx = lib.Context(wl.params())
+    st = [lib.State.empty(wl.P, DEV), lib.State.empty(wl.P, DEV)]
+    ctx.state_init(st[0])
+    out = lib.Outputs.empty(wl.P, DEV)
+    fdev = None if faulty is None else faulty.to(torch.uint8).to(DEV)
+    saved = {}
+    for n, f in enumerate(wl.frames):
+        prev, nxt = st[n % 2], st[(n + 1) % 2]
+        if n in keep:
+            s_in = oracle.State(*(t.double().cpu().numpy() for t in (prev.m, prev.v, prev.pi, prev.b)))
+        ctx.step_csr(f.row_ptr.to(DEV), f.toa.to(DEV), prev, nxt, out,
+                     pi_in=None if pi_in is None else pi_in[n].to(DEV), faulty=fdev)
+        if n in keep:
+            g = gpu_outputs_np(out)
+            g["mean"] = nxt.m.cpu().numpy()
+            saved[n] = (s_in, g)
+    assert ctx.last_device_status() == 0
+    rng = np.random.default_rng(77)
+    fl = None if faulty is None else faulty.numpy()
+    for n in frames:
+        s_in, g = saved[n]
+        pix = sample_pixels(wl, n, rng)
+        z = frame_hist(wl.frames[n], wl.T, pix)
+        _, ref = oracle.step(model, s_in, z, pixels=pix,
+                             pi_in=None if pi_in is None else pi_in[n].double().numpy(), faulty=fl)
+        sub = {k: v[pix] for k, v in g.items()}
+        rep = compare(sub, ref, model=model, state=s_in, z=z, pixels=pix, mean_rel=1e-4,
+                      var_rel=1e-3, int_rel=1e-3, faulty=fl, label=f"video {case} frame {n}")
+        print("video", case, n, len(pix), rep, flush=True)
