@@ -229,9 +229,11 @@ r3d_status r3d_min_divergence_msl(r3d_ctx *const *bands, int32_t nbands,
  * bins, 0 < sigma <= T (else R3D_EINVAL). depth: device float [P]; value:
  * device float [P] or NULL, (beta+1)/beta * sum_k f0(y_k|d)^beta at the
  * depth (natural-log units); grid_argmax: device int32 [P] or NULL, the grid
- * maximiser. A pixel without photons gets d_lo and 0. Evaluated in fp32
- * (terms below 2^-40 of one photon's peak are dropped). Asynchronous; a ToA
- * outside [0, T) sets R3D_ERANGE in the device error word. */
+ * maximiser. Evaluated in fp32; terms below 2^-40 of one photon's peak are
+ * dropped, so a pixel without photons, or whose photons all lie beyond that
+ * radius, sigma sqrt(80 / (beta log2(e))) bins, of every grid depth, gets
+ * d_lo and 0. Asynchronous; a ToA outside [0, T) sets R3D_ERANGE in the
+ * device error word. */
 r3d_status r3d_min_divergence_gauss(r3d_ctx *ctx, const int32_t *row_ptr, const int16_t *toa,
                                     double sigma, float *depth, float *value,
                                     int32_t *grid_argmax, void *stream);
