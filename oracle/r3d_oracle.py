@@ -290,7 +290,9 @@ def background_intensity(z: np.ndarray, model: Model, d_star: np.ndarray,
                          c_pix: Optional[np.ndarray] = None):
     """Undetected pixel: b = K / T and r = 0. Detected pixel: maximum
     likelihood (r, b) of z_t ~ Poisson(r s_t + b), s_t = irf[t - d* + c]
-    (zero outside the taps), r, b >= 0.
+    (zero outside the taps), r, b >= 0, with d* the integer depth given (the
+    filter passes its depth estimate, the posterior mean, rounded to the
+    nearest bin).
 
     Setting both score equations to zero gives K = r S + b T (S = sum s_t),
     so the optimum lies on b(r) = (K - r S) / T, r in [0, K/S]. The
@@ -420,7 +422,10 @@ def step(model: Model, state: State, z: np.ndarray, pixels=None,
     post = posterior_moments(ell, logf, grid)
     detected = pi_now[pixels] > 0.5
     zz = np.where(fault[:, None], 0, z)
-    r_hat, b_hat = background_intensity(zz, model, post["d_star"], detected, irf_sel, c_sel)
+    # the depth point estimate is the pseudo-posterior mean (Sec. II-E); the
+    # tabulated IRF is placed at its nearest bin (ties to even)
+    d_mle = np.rint(post["mean"])
+    r_hat, b_hat = background_intensity(zz, model, d_mle, detected, irf_sel, c_sel)
     b_hat = np.where(fault, state.b[pixels], b_hat)
 
     new = State(np.full(P, np.nan), np.full(P, np.nan), np.full(P, np.nan),
@@ -432,6 +437,7 @@ def step(model: Model, state: State, z: np.ndarray, pixels=None,
     out = dict(pixels=pixels, mean=post["mean"], var=post["var"],
                depth=np.where(detected, post["mean"], np.nan),
                argmax=post["d_star"].astype(np.int64), margin=post["margin"],
+               d_mle=d_mle.astype(np.int64),
                intensity=r_hat, background=b_hat,
                pi0_next=pi0_next(model, pi_now, pixels))
     return new, out

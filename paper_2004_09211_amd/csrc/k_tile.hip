@@ -498,6 +498,9 @@ __device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io,
   const float mu = mo.S1 / mo.S0;
   const int dstar = (int)mo.ref;
   const float mean = mo.ref + mu;
+  // the depth point estimate is the posterior mean (Sec. II-E): the MLE
+  // places the IRF at its nearest bin
+  const int dmle = (int)fminf(fmaxf(rintf(mean), (float)M.d_lo), (float)(M.d_lo + M.D - 1));
   const float var = fmaxf(mo.S2 / mo.S0 - mu * mu, 0.f);
 
   // ============================ a6 + a7 ============================
@@ -511,7 +514,7 @@ __device__ __forceinline__ void step_finish(const DevModel& M, const StepIO& io,
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int j = g + 4 * u;
-    const int t = dstar - M.c + j;
+    const int t = dmle - M.c + j;
     const bool in = j < M.W && t >= 0 && t < M.T;
     wz[u] = load_bin(M, L, g, t, in);
     ws[u] = in ? sh_irf[j] : 0.f;

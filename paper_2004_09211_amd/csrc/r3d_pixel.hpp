@@ -284,6 +284,8 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
   const float mu = S1 / S0;
   const int dstar = (int)ref;
   const float mean = ref + mu;
+  // the MLE's depth: the posterior mean's nearest bin (Sec. II-E)
+  const int dmle = (int)fminf(fmaxf(rintf(mean), (float)M.d_lo), (float)(M.d_lo + M.D - 1));
   const float var = fmaxf(S2 / S0 - mu * mu, 0.f);
 
   // ---- a6 + a7 ----
@@ -299,7 +301,7 @@ __device__ __forceinline__ void pixel_step(const DevModel& M, const StepIO& io, 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = lane + 64 * u;
-      const int t = dstar - M.c + j;
+      const int t = dmle - M.c + j;
       const bool in = j < M.W && t >= 0 && t < M.T;
       s[u] = in ? sh_irf[j] : 0.f;
       z[u] = in ? packed_count(hist, t) : 0.f;

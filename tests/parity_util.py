@@ -8,7 +8,8 @@ Comparison rules (see the test docstrings for where each applies):
 * posterior mean: |gpu - oracle| <= mean_rel * max(1, oracle posterior sd)
   + half an fp32 ulp of the oracle's mean (the output is stored in fp32);
 * variance: |gpu - oracle| <= var_rel * max(1, oracle variance);
-* reflectivity / background (where the argmax agrees):
+* reflectivity / background (where the posterior means round to the same
+  bin, the depth at which both sides place the IRF for the MLE):
   |gpu - oracle| <= int_rel * max(1, |oracle|);
 * prior presence probability: absolute 1e-5.
 """
@@ -89,7 +90,7 @@ def compare(gpu: dict, ref: dict, *, model=None, state=None, z=None, pixels=None
     dg, do = np.asarray(gpu["depth"]), ref["depth"]
     assert np.array_equal(np.isnan(dg), np.isnan(do)), f"{label}: detection pattern differs"
     if check_aux:
-        same = am_g == am_o
+        same = np.rint(np.asarray(mean, np.float64)) == ref["d_mle"]
         for k in ("intensity", "background"):
             e = np.abs(np.asarray(gpu[k], np.float64) - ref[k])[same]
             t = int_rel * np.maximum(1.0, np.abs(ref[k]))[same]

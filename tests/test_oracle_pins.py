@@ -423,3 +423,33 @@ def test_gaussian_irf_is_bin_integrated_pulse():
     np.testing.assert_allclose(irf, ref, rtol=1e-10, atol=1e-15)
     assert int(np.argmax(irf)) == c and abs(irf.sum() - 1.0) < 1e-14
     np.testing.assert_allclose(irf[c - 6:c], irf[c + 6:c:-1], rtol=1e-12)
+
+
+def test_step_places_the_mle_at_the_rounded_mean():
+    """Sec. II-E: the depth point estimate of a detected pixel is the
+    pseudo-posterior mean and the reflectivity is estimated with it. A pixel
+    with two equal returns (bins 20 and 44) has a two-mode posterior whose
+    argmax is one return and whose mean lies between them; the step's (r, b)
+    equal the Poisson maximum likelihood with the IRF placed at the mean's
+    nearest bin, found by scipy's bounded optimiser."""
+    m = make_model(rows=1, cols=1, T=64, W=9, c=4, beta=0.4, sigma=1.2)
+    z = np.zeros((1, 64), np.int64)
+    for d in (20, 44):
+        z[0, d - 4:d + 5] += np.round(12 * m.irf).astype(np.int64)
+    z[0, ::7] += 1
+    st = oracle.init_state(m)
+    _, out = oracle.step(m, st, z)
+    d_mle = int(out["d_mle"][0])
+    assert d_mle == int(np.rint(out["mean"][0])) and d_mle != int(out["argmax"][0])
+    t = np.arange(64)
+    tap = t - d_mle + m.c
+    s = np.where((tap >= 0) & (tap < m.W), m.irf[np.clip(tap, 0, m.W - 1)], 0.0)
+
+    def nll(x):
+        lam = x[0] * s + x[1]
+        return -(z[0] * np.log(np.maximum(lam, 1e-300)) - lam).sum()
+
+    res = optimize.minimize(nll, x0=[5.0, 0.5], bounds=[(0, None), (1e-12, None)],
+                            method="L-BFGS-B", options=dict(ftol=1e-15, gtol=1e-12))
+    assert out["intensity"][0] == pytest.approx(res.x[0], rel=1e-4)
+    assert out["background"][0] == pytest.approx(res.x[1], rel=1e-4)
