@@ -148,6 +148,26 @@ def counter_probe():
     print("counter probe done", flush=True)
 
 
+def sequence_probe(frames: int = 20):
+    """Counter driver for the steady frames: one sequence call of the
+    split-fp16 tile step over the first ``frames`` frames of the
+    256x256x4096 histograms (one launch per frame, each counted on its own)."""
+    import torch
+    import synth
+    from paper_2004_09211_amd import r3d
+    r3d.load()
+    dev = torch.device("cuda:0")
+    wl = synth.config4(seed=0, device=dev, frames=frames)
+    ctx = r3d.Context(wl.params(), "fp16x2")
+    st = [r3d.State.empty(wl.P, dev), r3d.State.empty(wl.P, dev)]
+    out = r3d.Outputs.empty(frames * wl.P, dev)
+    ctx.state_init(st[0])
+    ctx.run_hist([wl.hist[n] for n in range(frames)], st, out)
+    torch.cuda.synchronize()
+    assert ctx.last_device_status() == 0
+    print("sequence probe done", flush=True)
+
+
 COUNTER_KERNELS = {"k_tile_step<2,3>": "r3d::k_tile_step<2, 3>", "k_tile_step<0,3>": "r3d::k_tile_step<0, 3>",
                    "k_step_plain": "r3d::k_step_plain<false>", "k_batch": "r3d::k_batch(",
                    "k_adjoint": "k_adjoint(r3d::DevModel"}
@@ -682,6 +702,8 @@ def main():
     ap.add_argument("--grad-reps", type=int, default=5)
     ap.add_argument("--traffic-probe", action="store_true")
     ap.add_argument("--counter-probe", action="store_true")
+    ap.add_argument("--sequence-probe", action="store_true",
+                    help="20 frames of the tile step's sequence call, for per-launch counters")
     ap.add_argument("--summarize-trace", default="",
                     help="kernel-trace CSV of a rocprofv3 run of this script: print the tile "
                          "step's per-launch figures over the timed sequences and exit")
@@ -718,6 +740,9 @@ def main():
         return
     if args.counter_probe:
         counter_probe()
+        return
+    if args.sequence_probe:
+        sequence_probe()
         return
     leg = cpu = accuracy = None
     if not args.no_cpu_baseline:
