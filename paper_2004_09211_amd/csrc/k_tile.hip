@@ -424,24 +424,13 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
   // than 9 * 2^-kLiveGap relative and are skipped there.
   // The block keeps, per component, the tile range covering every pixel's
   // live interval (LDS min / max over the pixels).
+  // Each lane group takes its own components (k = g, g + 4, and k = 8 for
+  // the first group), so the loop runs three times rather than nine; the
+  // LDS minima, maxima and or-ed bits do not depend on which lane adds them.
   if (lane < 9) {
     B.trange[lane] = 0x7fffffff;
     B.trange[9 + lane] = -1;
   }
-  wave_sync();
-  if (L.valid && g == 0) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      if (!(C.w2[k] >= theta - kLiveGap)) continue;
-      const float R = __builtin_amdgcn_sqrtf((C.w2[k] - theta + kLiveGap) * fast_rcp(C.k2[k])) + 2.0f;
-      const float lo = fmaxf(C.m[k] - R, (float)M.d_lo);
-      const float hi = fminf(C.m[k] + R, (float)dhi);
-      if (!(lo <= hi)) continue;
-      atomicMin(&B.trange[k], ((int)floorf(lo) - M.d_lo) >> 4);
-      atomicMax(&B.trange[9 + k], ((int)ceilf(hi) - M.d_lo) >> 4);
-    }
-  }
-
   // candidate tiles and pairs (LDS bit masks, or-ed by the lanes)
   const int nwords = G.mask_words + G.pair_words + 1;  // the pair bits are read 64 at a time
   for (int w = lane; w < nwords; w += 64) B.tmask[w] = 0u;
@@ -454,17 +443,37 @@ __device__ __forceinline__ void step_prep(const DevModel& M, const TileGeom& G, 
       atomicOr(&mk[w], bits);
     }
   };
+  // component g + 4 it of the lane's group (it < 2), component 8 (it == 2)
+  auto pick = [&](const float (&a)[9], int it) __attribute__((always_inline)) -> float {
+    if (it == 2) return a[8];
+    const float x0 = a[4 * it], x1 = a[4 * it + 1], x2 = a[4 * it + 2], x3 = a[4 * it + 3];
+    return g == 0 ? x0 : (g == 1 ? x1 : (g == 2 ? x2 : x3));
+  };
   if (L.valid) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      if ((k & 3) != g || !(C.w2[k] >= theta)) continue;
-      const float R = __builtin_amdgcn_sqrtf((C.w2[k] - theta) * fast_rcp(C.k2[k])) + 2.0f;
-      const float lo = fmaxf(floorf(C.m[k] - R), (float)M.d_lo);
-      const float hi = fminf(ceilf(C.m[k] + R), (float)dhi);
-      if (!(lo <= hi)) continue;
-      const int ta = ((int)lo - M.d_lo) >> 4, tb = ((int)hi - M.d_lo) >> 4;
-      set_bits(B.tmask, ta, tb);
-      set_bits(B.pmask, ta >> 1, tb >> 1);
+    for (int it = 0; it < 3; ++it) {
+      if (it == 2 && g != 0) continue;
+      const int k = it == 2 ? 8 : g + 4 * it;
+      const float w2 = pick(C.w2, it), mk = pick(C.m, it), rk = fast_rcp(pick(C.k2, it));
+      if (w2 >= theta - kLiveGap) {
+        const float R = __builtin_amdgcn_sqrtf((w2 - theta + kLiveGap) * rk) + 2.0f;
+        const float lo = fmaxf(mk - R, (float)M.d_lo);
+        const float hi = fminf(mk + R, (float)dhi);
+        if (lo <= hi) {
+          atomicMin(&B.trange[k], ((int)floorf(lo) - M.d_lo) >> 4);
+          atomicMax(&B.trange[9 + k], ((int)ceilf(hi) - M.d_lo) >> 4);
+        }
+      }
+      if (w2 >= theta) {
+        const float R = __builtin_amdgcn_sqrtf((w2 - theta) * rk) + 2.0f;
+        const float lo = fmaxf(floorf(mk - R), (float)M.d_lo);
+        const float hi = fminf(ceilf(mk + R), (float)dhi);
+        if (lo <= hi) {
+          const int ta = ((int)lo - M.d_lo) >> 4, tb = ((int)hi - M.d_lo) >> 4;
+          set_bits(B.tmask, ta, tb);
+          set_bits(B.pmask, ta >> 1, tb >> 1);
+        }
+      }
     }
   }
   wave_sync();
