@@ -178,15 +178,27 @@ __device__ __forceinline__ float pi0_next_at(const DevModel& M, const float* __r
                                              const uint8_t* __restrict__ faulty, int p) {
   const int r = p / M.cols;
   const int col = p - r * M.cols;
+  // without presence probabilities or faulty pixels every in-frame
+  // neighbour has pi = 1: one logit serves them all
+  const bool all_one = !pi_in && !faulty;
+  float logit1 = 0.f;
+  if (all_one) {
+    const float pk = fminf(fmaxf(1.0f, 1e-6f), 1.0f - 1e-6f);
+    logit1 = fast_log2(pk) - fast_log2(1.0f - pk);
+  }
   float acc = 0.f;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     if (M.nu[k] == 0.f) continue;
     const int rr = r + k / 3 - 1, cc = col + k % 3 - 1;
     if (rr < 0 || rr >= M.rows || cc < 0 || cc >= M.cols) continue;
-    float pk = pi_now_at(pi_in, faulty, rr * M.cols + cc);
-    pk = fminf(fmaxf(pk, 1e-6f), 1.0f - 1e-6f);
-    acc += M.nu[k] * (fast_log2(pk) - fast_log2(1.0f - pk));  // logit in log2 units
+    float lg = logit1;  // logit in log2 units
+    if (!all_one) {
+      float pk = pi_now_at(pi_in, faulty, rr * M.cols + cc);
+      pk = fminf(fmaxf(pk, 1e-6f), 1.0f - 1e-6f);
+      lg = fast_log2(pk) - fast_log2(1.0f - pk);
+    }
+    acc += M.nu[k] * lg;
   }
   return fast_rcp(1.0f + fast_exp2(-acc));
 }
