@@ -450,6 +450,93 @@ def run_video(args):
                 workload="128x128 x 50 frames, T=1500, photon lists (CSR int16), fp32 per-pixel step")
 
 
+def run_rows(args):
+    """The minimum-divergence and per-pixel-IRF rows, each timed on a
+    workload shaped like the paper's (events on the launch stream, median
+    over repetitions, inputs resident on the device):
+    * min_divergence: the prior-free argmax of the split-fp16 cost on the
+      256x256 x 4096-bin histograms (frames 0-3 in turn), HBM-bound;
+    * min_divergence_msl: two bands of that size (the second band with a
+      sigma=4 Gaussian IRF of the same 64 taps, its counts those of the next
+      frame);
+    * min_divergence_gauss: the continuous Gaussian-IRF maximiser on the
+      128x128 photon-list video (sigma=3 bins), one launch per frame;
+    * step_pirf: the 128x128 x 50-frame photon-list video with a per-pixel
+      Gaussian IRF (sigma uniform in [2.5, 3.5] bins, 31 taps), one step per
+      frame."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2004_09211_amd import r3d
+
+    dev = torch.device("cuda:0")
+    reps = 5
+
+    def timed(fn, n):
+        times = []
+        for i in range(reps + 1):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for k in range(n):
+                fn(k)
+            e1.record()
+            torch.cuda.synchronize()
+            if i > 0:
+                times.append(e0.elapsed_time(e1) / n)
+        return sorted(times)[len(times) // 2]
+
+    out = {}
+    wl = synth.config4(seed=0, device=dev, frames=4)
+    P, T = wl.P, wl.T
+    ctx = r3d.Context(wl.params(), "fp16x2")
+    am = torch.empty(P, dtype=torch.int32, device=dev)
+    val = torch.empty(P, dtype=torch.float32, device=dev)
+    ms = timed(lambda k: ctx.min_divergence(wl.hist[k % 4], am, val), 8)
+    bts = P * (2 * T + 8)
+    out["min_divergence"] = dict(
+        ms_per_launch=round(ms, 4), value=round(P / (ms * 1e-3), 1), unit="pixels/s",
+        bytes_per_launch=bts, achieved_gbs=round(bts / (ms * 1e-3) / 1e9, 1),
+        frac_hbm=round(bts / (ms * 1e-3) / 8e12, 4),
+        workload="256x256 pixels, T=4096 fp16 histograms, W=64, beta=0.5, split fp16")
+    p2 = dict(wl.params(), irf=synth.gaussian_irf(4.0, wl.W, wl.c))
+    bands = [ctx, r3d.Context(p2, "fp16x2")]
+    ms = timed(lambda k: r3d.min_divergence_msl(bands, [wl.hist[k % 4], wl.hist[(k + 1) % 4]], am, val), 8)
+    bts = P * (2 * 2 * T + 8)
+    out["min_divergence_msl"] = dict(
+        ms_per_launch=round(ms, 4), value=round(P / (ms * 1e-3), 1), unit="pixels/s",
+        bytes_per_launch=bts, achieved_gbs=round(bts / (ms * 1e-3) / 1e9, 1),
+        frac_hbm=round(bts / (ms * 1e-3) / 8e12, 4),
+        workload="2 bands of 256x256 pixels, T=4096 fp16 histograms, 64-tap IRFs (sigma 6 and 4)")
+    if ctx.last_device_status() != 0 or bands[1].last_device_status() != 0:
+        raise RuntimeError("minimum-divergence leg reported a device error")
+    del wl, ctx, bands
+    wv = synth.config2(seed=0, device=dev)
+    cv = r3d.Context(wv.params())
+    frames = [(f.row_ptr, f.toa) for f in wv.frames]
+    N = len(frames)
+    dep = torch.empty(wv.P, dtype=torch.float32, device=dev)
+    vv = torch.empty(wv.P, dtype=torch.float32, device=dev)
+    ga = torch.empty(wv.P, dtype=torch.int32, device=dev)
+    ms = timed(lambda k: cv.min_divergence_gauss(*frames[k % N], 3.0, dep, vv, ga), N)
+    out["min_divergence_gauss"] = dict(
+        ms_per_launch=round(ms, 4), value=round(wv.P / (ms * 1e-3), 1), unit="pixels/s",
+        workload="128x128 photon lists (CSR int16), T=1500, Gaussian IRF sigma=3 bins, continuous depth")
+    rng = np.random.default_rng(5)
+    sig = rng.uniform(2.5, 3.5, wv.P)
+    irf_pix = torch.as_tensor(np.stack([synth.gaussian_irf(x, wv.W, wv.c) for x in sig]), device=dev)
+    st = [r3d.State.empty(wv.P, dev), r3d.State.empty(wv.P, dev)]
+    o = r3d.Outputs.empty(wv.P, dev)
+    cv.state_init(st[0])
+    ms = timed(lambda k: cv.step_pirf(frames[k % N], irf_pix, st[k % 2], st[(k + 1) % 2], o), N)
+    out["step_pirf"] = dict(
+        ms_per_frame=round(ms, 4), value=round(wv.P / (ms * 1e-3), 1), unit="pixel-frames/s",
+        workload="128x128 x 50 frames, T=1500, photon lists, per-pixel Gaussian IRFs (sigma 2.5..3.5, 31 taps)")
+    if cv.last_device_status() != 0:
+        raise RuntimeError("per-pixel-IRF leg reported a device error")
+    return out
+
+
 def run_batched(args):
     """Uneven batch: 64 sequences x 10 frames (resolutions 32..256 squared,
     500..4000 bins, log-normal photon counts) through one persistent launch
@@ -716,6 +803,8 @@ def main():
                     help="output directories of the two rocprofv3 --pmc runs of --traffic-probe "
                          "(FETCH_SIZE, WRITE_SIZE): write the traffic record and exit")
     ap.add_argument("--no-video", action="store_true")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the minimum-divergence and per-pixel-IRF legs")
     ap.add_argument("--video-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -758,6 +847,7 @@ def main():
     video = None if args.no_video else run_video(args)
     batched = None if args.no_batched else run_batched(args)
     gradient = None if args.no_grad else run_grad(args)
+    rows = None if args.no_rows else run_rows(args)
     line = dict(
         metric=METRIC, value=round(res["value"], 1), unit="pixel-frames/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=round(res["ms_per_step"], 4),
@@ -778,7 +868,7 @@ def main():
                          counters=res["plain"]["counters"],
                          speedup=round(res["value"] / res["plain"]["value"], 3))),
         roofline=res["roofline"], accuracy=accuracy, cpu_baseline=cpu, video=video,
-        batched=batched, gradient=gradient)
+        batched=batched, gradient=gradient, rows=rows)
     print(json.dumps(line), flush=True)
 
 

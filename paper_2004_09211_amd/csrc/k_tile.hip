@@ -1223,10 +1223,15 @@ __global__ void __launch_bounds__(256) k_tile_cost(DevModel M, TileGeom G, const
 // multispectral one maximises sum_l log(c_l(d) / K_l), c_l the band's
 // correlation with its own irf^beta and K_l its photon count (Appendix,
 // eq. div_MSL), bands without photons left out. One wavefront per 4x4 pixel
-// block: a first sweep counts each band's photons (and validates the counts),
-// then every pair's exact cost (split fp16 on the matrix cores, or fp32) is
-// reduced to a running argmax per lane (the lowest depth among equal
-// values), merged over the pixel's four lanes.
+// block streams each band's histograms once through a register ring (each
+// 32-bin block loaded once, kTilePF pairs ahead for one band, one for
+// several), computes every pair's exact cost (split fp16 on the matrix
+// cores, or fp32) and reduces it to a running argmax per lane (the lowest
+// depth among equal values), merged over the pixel's four lanes. The
+// photon counts and the count validation (integers in [0, 2048]) ride on
+// the stream for one band; several bands need their counts first (a band
+// without photons is left out of the sum), so they are counted in a sweep of
+// their own.
 template <int kEng, int NBP, bool kMsl>
 __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1237,92 +1242,209 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
   const int idx = blockIdx.x * 4 + wave;
   if (idx >= G0.nblk) return;
   _Float16* ring_lds = reinterpret_cast<_Float16*>(smem + A.nb * A.lds_band) + wave * 16 * kRingStride;
+  constexpr int NBL = kMsl ? kMaxBands : 1;
+  constexpr int RING = NBP + (kMsl ? 1 : kTilePF<kEng>);
 
-  // photon count of each band (every block once) and count validation:
-  // integers in [0, 2048]
-  float Kb[kMaxBands];
-  unsigned mask = 0u;
-  unsigned bad = 0u;
-  for (int l = 0; l < A.nb; ++l) {
-    const LanePix L = lane_pixel(A.M[l], A.G[l], A.hist[l], nullptr, idx, i16, g);
-    float ks = 0.f;
-    for (int kb = 0; kb < A.G[l].nkb; ++kb) {
-      const half8 v = load_block(A.M[l], L, g, kb);
-      const ushort8 u = __builtin_bit_cast(ushort8, v);
+  // photon counts by fp16 dot products with ones (exact integer sums), count
+  // validation by the packed maximum of the raw fp16 bits and the or of the
+  // fractional parts
+  ushort2 vmax = {0, 0};
+  unsigned vfrac = 0u;
+  auto account = [&](half8 v, float& kv) __attribute__((always_inline)) {
+    const ushort8 u = __builtin_bit_cast(ushort8, v);
+    const ushort2 m01 = __builtin_elementwise_max(ushort2{u[0], u[1]}, ushort2{u[2], u[3]});
+    const ushort2 m23 = __builtin_elementwise_max(ushort2{u[4], u[5]}, ushort2{u[6], u[7]});
+    vmax = __builtin_elementwise_max(vmax, __builtin_elementwise_max(m01, m23));
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        if (!fp16_count_ok(u[s])) bad |= kErrOverflow;
-        ks += (float)v[s];
-      }
-    }
-    Kb[l] = group_sum<16, 32>(ks);
-    mask |= (Kb[l] > 0.f ? 1u : 0u) << l;
-  }
-  if (bad) atomicOr(M0.err, bad);
+    for (int q = 0; q < 4; ++q)
+      vfrac |= __builtin_bit_cast(unsigned, half2{(_Float16)__builtin_amdgcn_fracth(v[2 * q]),
+                                                  (_Float16)__builtin_amdgcn_fracth(v[2 * q + 1])});
+    const half2 one2 = {(_Float16)1.f, (_Float16)1.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kv = __builtin_amdgcn_fdot2(half2{v[2 * q], v[2 * q + 1]}, one2, kv, false);
+  };
 
-  const LanePix L0 = lane_pixel(M0, G0, A.hist[0], nullptr, idx, i16, g);
+  float Kv[NBL];
+  LanePix Lb[NBL];
+#pragma unroll
+  for (int l = 0; l < NBL; ++l) {
+    Kv[l] = 0.f;
+    if (l >= A.nb) continue;
+    Lb[l] = lane_pixel(A.M[l], A.G[l], A.hist[l], nullptr, idx, i16, g);
+    // blocks of [0, T) that no depth window reaches still hold photons
+    const TileGeom& Gl = A.G[l];
+    for (int kb = 0; kb < Gl.nkb; ++kb)
+      if (kb < Gl.kbA0 || kb > Gl.kb_last) account(load_block(A.M[l], Lb[l], g, kb), Kv[l]);
+  }
+
+  const bool valid = Lb[0].valid;
   const int dhi = M0.d_lo + M0.D - 1;
   float best = -INFINITY;
   int bidx = 0x7fffffff;
-  for (int m = 0; m < G0.npairs; ++m) {
-    floatx4 J0 = {0.f, 0.f, 0.f, 0.f}, J1 = J0;
-    for (int l = 0; l < A.nb; ++l) {
-      const DevModel& Ml = A.M[l];
-      const TileGeom& Gl = A.G[l];
-      const LanePix L = lane_pixel(Ml, Gl, A.hist[l], nullptr, idx, i16, g);
-      half8 blk[NBP];
-#pragma unroll
-      for (int b = 0; b < NBP; ++b) blk[b] = load_block(Ml, L, g, Gl.kbA0 + m + b);
-      if constexpr (kEng == kEngValu) {
-        wave_sync();
-#pragma unroll
-        for (int b = 0; b < NBP; ++b) ring_store(ring_lds, i16, g, Gl.kbA0 + m + b, blk[b]);
-        wave_sync();
-      }
-      const half8* sA = reinterpret_cast<const half8*>(smem + l * A.lds_band + Gl.lda_band);
-      floatx4 c0, c1;
-      pair_cost<kEng, NBP>(Ml, sA, ring_lds, lane, m, blk, c0, c1);
-      if constexpr (kMsl) {
-        const bool use = (mask >> l) & 1u;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          J0[q] += !use ? 0.f : (c0[q] > 0.f ? fast_log2(c0[q]) : -INFINITY);
-          J1[q] += !use ? 0.f : (c1[q] > 0.f ? fast_log2(c1[q]) : -INFINITY);
-        }
-      } else {
-        J0 = c0;
-        J1 = c1;
-      }
-    }
+  // one band on the matrix cores: the fp16-hi A operands stay in registers
+  // (the low parts are read from LDS), halving the LDS reads of each pair
+  constexpr bool kHiRegs = !kMsl && kEng != kEngValu;
+  half8 Ahi[2][NBP];
+  if constexpr (kHiRegs) {
+    const half8* sA0 = reinterpret_cast<const half8*>(smem + G0.lda_band);
 #pragma unroll
     for (int tau = 0; tau < 2; ++tau)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int d = M0.d_lo + 32 * m + 16 * tau + 4 * g + q;
-        const float v = tau ? J1[q] : J0[q];
-        if (L0.valid && d <= dhi && (v > best || (bidx == 0x7fffffff && v == best))) {
-          best = v;
-          bidx = d - M0.d_lo;
+      for (int b = 0; b < NBP; ++b) Ahi[tau][b] = a_op(sA0, NBP, 0, tau, b, lane);
+  }
+  // One pass over the band blocks: the running argmax of the cost (one band)
+  // or of the sum over the bands in ``mask`` (per pixel), counting the
+  // photons when ``counting``.
+  half8 ring[NBL][RING];
+  auto stream = [&](unsigned mask, bool counting) __attribute__((always_inline)) {
+    best = -INFINITY;
+    bidx = 0x7fffffff;
+#pragma unroll
+    for (int l = 0; l < NBL; ++l) {
+      if (l >= A.nb) continue;
+#pragma unroll
+      for (int x = 0; x < RING - 1; ++x) {
+        const int kb = A.G[l].kbA0 + x;
+        ring[l][x] = load_block(A.M[l], Lb[l], g, kb <= A.G[l].kb_last ? kb : -1);
+      }
+    }
+  for (int m0 = 0; m0 < G0.npairs; m0 += RING) {
+#pragma unroll
+    for (int u = 0; u < RING; ++u) {
+      const int m = m0 + u;
+#pragma unroll
+      for (int l = 0; l < NBL; ++l) {
+        if (l >= A.nb) continue;
+        const int kb = A.G[l].kbA0 + m + RING - 1;
+        ring[l][(u + RING - 1) % RING] = load_block(A.M[l], Lb[l], g, kb <= A.G[l].kb_last ? kb : -1);
+      }
+      if (m < G0.npairs) {
+        floatx4 J0 = {0.f, 0.f, 0.f, 0.f}, J1 = J0;
+#pragma unroll
+        for (int l = 0; l < NBL; ++l) {
+          if (l >= A.nb) continue;
+          const DevModel& Ml = A.M[l];
+          const TileGeom& Gl = A.G[l];
+          half8 blk[NBP];
+#pragma unroll
+          for (int b = 0; b < NBP; ++b) blk[b] = ring[l][(u + b) % RING];
+          if (counting) {
+            // every block of the band counted once: the first NBP - 1 with
+            // pair 0, then the last block of each pair
+            if (m == 0) {
+#pragma unroll
+              for (int b = 0; b < NBP - 1; ++b) account(blk[b], Kv[l]);
+            }
+            account(blk[NBP - 1], Kv[l]);
+          }
+          if constexpr (kEng == kEngValu) {
+            wave_sync();
+#pragma unroll
+            for (int b = 0; b < NBP; ++b) ring_store(ring_lds, i16, g, Gl.kbA0 + m + b, blk[b]);
+            wave_sync();
+          }
+          const half8* sA = reinterpret_cast<const half8*>(smem + l * A.lds_band + Gl.lda_band);
+          floatx4 c0, c1;
+          if constexpr (kHiRegs) {
+            floatx4 h0 = {0.f, 0.f, 0.f, 0.f}, h1 = h0;
+#pragma unroll
+            for (int b = 0; b < NBP; ++b) {
+              h0 = mfma16(Ahi[0][b], blk[b], h0);
+              h1 = mfma16(Ahi[1][b], blk[b], h1);
+            }
+            if constexpr (kEng == kEngMfma16x2) {
+              half8 Alo[2][NBP];
+#pragma unroll
+              for (int b = 0; b < NBP; ++b) {
+                Alo[0][b] = a_op(sA, NBP, 1, 0, b, lane);
+                Alo[1][b] = a_op(sA, NBP, 1, 1, b, lane);
+              }
+              floatx4 l0 = {0.f, 0.f, 0.f, 0.f}, l1 = l0;
+#pragma unroll
+              for (int b = 0; b < NBP; ++b) {
+                l0 = mfma16(Alo[0][b], blk[b], l0);
+                l1 = mfma16(Alo[1][b], blk[b], l1);
+              }
+              c0 = h0 + l0;
+              c1 = h1 + l1;
+            } else {
+              c0 = h0;
+              c1 = h1;
+            }
+          } else {
+            pair_cost<kEng, NBP>(Ml, sA, ring_lds, lane, m, blk, c0, c1);
+          }
+          if constexpr (kMsl) {
+            const bool use = (mask >> l) & 1u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              J0[q] += !use ? 0.f : (c0[q] > 0.f ? fast_log2(c0[q]) : -INFINITY);
+              J1[q] += !use ? 0.f : (c1[q] > 0.f ? fast_log2(c1[q]) : -INFINITY);
+            }
+          } else {
+            J0 = c0;
+            J1 = c1;
+          }
+        }
+        // each tile's maximum over the lane's four depths (the lowest among
+        // equal values; depths past the grid are -inf), then the running one
+#pragma unroll
+        for (int tau = 0; tau < 2; ++tau) {
+          const int d0 = M0.d_lo + 32 * m + 16 * tau + 4 * g;
+          float mt = -INFINITY;
+          int qt = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float v = d0 + q <= dhi ? (tau ? J1[q] : J0[q]) : -INFINITY;
+            if (v > mt) {
+              mt = v;
+              qt = q;
+            }
+          }
+          if (valid && d0 <= dhi && (mt > best || (bidx == 0x7fffffff && mt == best))) {
+            best = mt;
+            bidx = d0 + qt - M0.d_lo;
+          }
         }
       }
+    }
   }
+  };
+  // Several bands: the pass assumes every band of every pixel holds photons;
+  // a block where some band of some pixel has none (that band leaves the
+  // sum) runs the pass again with the pixels' own bands.
+  stream(kMsl ? (1u << A.nb) - 1u : 1u, true);
+  float Kb[NBL];
+  unsigned mask = 0u;
+#pragma unroll
+  for (int l = 0; l < NBL; ++l) {
+    Kb[l] = group_sum<16, 32>(Kv[l]);
+    if (l < A.nb) mask |= (Kb[l] > 0.f ? 1u : 0u) << l;
+  }
+  if constexpr (kMsl) {
+    if (__any(valid && mask != (1u << A.nb) - 1u)) stream(mask, false);
+  }
+  // above 2048, negative (sign bit set) or not an integer
+  if (vmax[0] > 0x6800u || vmax[1] > 0x6800u || vfrac != 0) atomicOr(M0.err, kErrOverflow);
   group_argmax<16, 32>(best, bidx);
   if (bidx == 0x7fffffff) bidx = 0;
-  if (L0.valid && g == 0) {
+  if (valid && g == 0) {
     float val;
     if constexpr (kMsl) {
       // log2 of the raw cost is log2 c_l + 11 for the split engine (its
       // high part is scaled by 2^11)
       const float sh = kEng == kEngMfma16x2 ? 11.f : 0.f;
       float off = 0.f;
-      for (int l = 0; l < A.nb; ++l)
-        if ((mask >> l) & 1u) off += sh + fast_log2(Kb[l]);
+#pragma unroll
+      for (int l = 0; l < NBL; ++l)
+        if (l < A.nb && ((mask >> l) & 1u)) off += sh + fast_log2(Kb[l]);
       val = best == -INFINITY ? -INFINITY : (best - off) * kLn2;
     } else {
+      (void)Kb;
       val = best * M0.scale2 * (kEng == kEngMfma16x2 ? (1.0f / 2048.0f) : 1.0f) * kLn2;
     }
-    A.argmax[L0.p] = M0.d_lo + bidx;
-    if (A.value) A.value[L0.p] = val;
+    A.argmax[Lb[0].p] = M0.d_lo + bidx;
+    if (A.value) A.value[Lb[0].p] = val;
   }
 }
 
