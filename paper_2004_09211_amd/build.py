@@ -28,9 +28,13 @@ CXXFLAGS = [
 # per-file flags: the tile kernels take block-wide minima, maxima and bit
 # masks with LDS atomics from up to 16 lanes on one address; the compiler's
 # atomic optimizer turns each into a loop over the active lanes, far slower
-# than the LDS unit serialising them
+# than the LDS unit serialising them. The matrix products accumulate in
+# ordinary VGPRs rather than the accumulation registers: the estimate
+# kernels otherwise copy every product out with one move per register (the
+# filter step compiles to the same code either way).
 FILE_FLAGS = {
-    "k_tile.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+    "k_tile.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
+                   "-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 

@@ -1229,20 +1229,24 @@ __global__ void __launch_bounds__(256) k_tile_cost(DevModel M, TileGeom G, const
 // cores, or fp32) and reduces it to a running argmax per lane (the lowest
 // depth among equal values), merged over the pixel's four lanes. The
 // photon counts and the count validation (integers in [0, 2048]) ride on
-// the stream for one band; several bands need their counts first (a band
-// without photons is left out of the sum), so they are counted in a sweep of
-// their own.
-template <int kEng, int NBP, bool kMsl>
+// the stream. The kernel holds kNBL bands' rings and operands (one, two or
+// kMaxBands); every ring load is issued unconditionally, a band past the
+// last reading nothing, so that the compiler's wait counts stay exact
+// across the unrolled ring (a load under a branch costs a wait for every
+// load in flight).
+template <int kEng, int NBP, bool kMsl, int kNBL>
 __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
+  static_assert(kMsl ? (kNBL >= 1 && kNBL <= kMaxBands) : kNBL == 1, "bands held");
   extern __shared__ __align__(16) unsigned char smem[];
-  for (int l = 0; l < A.nb; ++l) tile_prologue<kEng, NBP>(A.M[l], A.G[l], smem + l * A.lds_band);
+  const int nb = kMsl ? A.nb : 1;
+  for (int l = 0; l < nb; ++l) tile_prologue<kEng, NBP>(A.M[l], A.G[l], smem + l * A.lds_band);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i16 = lane & 15, g = lane >> 4;
   const DevModel& M0 = A.M[0];
   const TileGeom& G0 = A.G[0];
   const int idx = blockIdx.x * 4 + wave;
   if (idx >= G0.nblk) return;
-  _Float16* ring_lds = reinterpret_cast<_Float16*>(smem + A.nb * A.lds_band) + wave * 16 * kRingStride;
-  constexpr int NBL = kMsl ? kMaxBands : 1;
+  _Float16* ring_lds = reinterpret_cast<_Float16*>(smem + nb * A.lds_band) + wave * 16 * kRingStride;
+  constexpr int NBL = kNBL;
   constexpr int RING = NBP + (kMsl ? 1 : kTilePF<kEng>);
 
   // photon counts by fp16 dot products with ones (exact integer sums), count
@@ -1269,7 +1273,12 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
 #pragma unroll
   for (int l = 0; l < NBL; ++l) {
     Kv[l] = 0.f;
-    if (l >= A.nb) continue;
+    if (l >= nb) {
+      // a band past the last: its ring loads read nothing
+      Lb[l] = Lb[0];
+      Lb[l].klim = 0u;
+      continue;
+    }
     Lb[l] = lane_pixel(A.M[l], A.G[l], A.hist[l], nullptr, idx, i16, g);
     // blocks of [0, T) that no depth window reaches still hold photons
     const TileGeom& Gl = A.G[l];
@@ -1278,9 +1287,8 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
   }
 
   const bool valid = Lb[0].valid;
-  const int dhi = M0.d_lo + M0.D - 1;
   float best = -INFINITY;
-  int bidx = 0x7fffffff;
+  int bidx = 0;
   // one band on the matrix cores: the fp16-hi A operands stay in registers
   // (the low parts are read from LDS), halving the LDS reads of each pair
   constexpr bool kHiRegs = !kMsl && kEng != kEngValu;
@@ -1298,10 +1306,9 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
   half8 ring[NBL][RING];
   auto stream = [&](unsigned mask, bool counting) __attribute__((always_inline)) {
     best = -INFINITY;
-    bidx = 0x7fffffff;
+    bidx = 0;
 #pragma unroll
     for (int l = 0; l < NBL; ++l) {
-      if (l >= A.nb) continue;
 #pragma unroll
       for (int x = 0; x < RING - 1; ++x) {
         const int kb = A.G[l].kbA0 + x;
@@ -1314,7 +1321,6 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
       const int m = m0 + u;
 #pragma unroll
       for (int l = 0; l < NBL; ++l) {
-        if (l >= A.nb) continue;
         const int kb = A.G[l].kbA0 + m + RING - 1;
         ring[l][(u + RING - 1) % RING] = load_block(A.M[l], Lb[l], g, kb <= A.G[l].kb_last ? kb : -1);
       }
@@ -1322,7 +1328,7 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
         floatx4 J0 = {0.f, 0.f, 0.f, 0.f}, J1 = J0;
 #pragma unroll
         for (int l = 0; l < NBL; ++l) {
-          if (l >= A.nb) continue;
+          if (l >= nb) continue;
           const DevModel& Ml = A.M[l];
           const TileGeom& Gl = A.G[l];
           half8 blk[NBP];
@@ -1386,25 +1392,32 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
             J1 = c1;
           }
         }
-        // each tile's maximum over the lane's four depths (the lowest among
-        // equal values; depths past the grid are -inf), then the running one
-#pragma unroll
-        for (int tau = 0; tau < 2; ++tau) {
-          const int d0 = M0.d_lo + 32 * m + 16 * tau + 4 * g;
-          float mt = -INFINITY;
-          int qt = 0;
+        // depths past the grid (only the last pair reaches them) are -inf
+        if (m == G0.npairs - 1) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float v = d0 + q <= dhi ? (tau ? J1[q] : J0[q]) : -INFINITY;
-            if (v > mt) {
-              mt = v;
-              qt = q;
-            }
+            const int o = 32 * m + 4 * g + q;
+            J0[q] = o < M0.D ? J0[q] : -INFINITY;
+            J1[q] = o + 16 < M0.D ? J1[q] : -INFINITY;
           }
-          if (valid && d0 <= dhi && (mt > best || (bidx == 0x7fffffff && mt == best))) {
-            best = mt;
-            bidx = d0 + qt - M0.d_lo;
-          }
+        }
+        // the pair's maximum over the lane's eight depths and the first
+        // depth that attains it (depth offsets: 16 tau + q past 32 m + 4 g),
+        // then the running one; strict comparisons keep the lowest depth
+        // among equal values
+        int off[2];
+        float mt[2];
+#pragma unroll
+        for (int tau = 0; tau < 2; ++tau) {
+          const floatx4 J = tau ? J1 : J0;
+          mt[tau] = __builtin_fmaxf(__builtin_fmaxf(J[0], J[1]), __builtin_fmaxf(J[2], J[3]));
+          off[tau] = 16 * tau + (J[0] == mt[tau] ? 0 : J[1] == mt[tau] ? 1 : J[2] == mt[tau] ? 2 : 3);
+        }
+        const bool hi = mt[1] > mt[0];
+        const float mp = hi ? mt[1] : mt[0];
+        if (mp > best) {
+          best = mp;
+          bidx = 32 * m + 4 * g + (hi ? off[1] : off[0]);
         }
       }
     }
@@ -1419,7 +1432,7 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
 #pragma unroll
   for (int l = 0; l < NBL; ++l) {
     Kb[l] = group_sum<16, 32>(Kv[l]);
-    if (l < A.nb) mask |= (Kb[l] > 0.f ? 1u : 0u) << l;
+    if (l < nb) mask |= (Kb[l] > 0.f ? 1u : 0u) << l;
   }
   if constexpr (kMsl) {
     if (__any(valid && mask != (1u << A.nb) - 1u)) stream(mask, false);
@@ -1427,7 +1440,6 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
   // above 2048, negative (sign bit set) or not an integer
   if (vmax[0] > 0x6800u || vmax[1] > 0x6800u || vfrac != 0) atomicOr(M0.err, kErrOverflow);
   group_argmax<16, 32>(best, bidx);
-  if (bidx == 0x7fffffff) bidx = 0;
   if (valid && g == 0) {
     float val;
     if constexpr (kMsl) {
@@ -1560,16 +1572,16 @@ hipError_t launch_cost_tile(const DevModel& M0, int engine, const uint16_t* hist
   return hipErrorInvalidValue;
 }
 
-template <int kEng, bool kMsl>
+template <int kEng, bool kMsl, int kNBL>
 static hipError_t launch_mindiv_eng(const MindivArgs& A, int nbp, size_t lds, hipStream_t s) {
   const dim3 grid((A.G[0].nblk + 3) / 4), block(256);
   switch (nbp) {
 #define R3D_MD_CASE(N)                                                                  \
   case N:                                                                               \
     if (lds > 65536)                                                                    \
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mindiv<kEng, N, kMsl>), \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
-    hipLaunchKernelGGL((k_mindiv<kEng, N, kMsl>), grid, block, lds, s, A);             \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mindiv<kEng, N, kMsl, kNBL>), \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);        \
+    hipLaunchKernelGGL((k_mindiv<kEng, N, kMsl, kNBL>), grid, block, lds, s, A);             \
     break;
     R3D_MD_CASE(2)
     R3D_MD_CASE(3)
@@ -1579,6 +1591,14 @@ static hipError_t launch_mindiv_eng(const MindivArgs& A, int nbp, size_t lds, hi
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// the multispectral kernel holds the registers of two bands, or of all
+template <int kEng>
+static hipError_t launch_mindiv_bands(const MindivArgs& A, bool msl, int nbp, size_t lds, hipStream_t s) {
+  if (!msl) return launch_mindiv_eng<kEng, false, 1>(A, nbp, lds, s);
+  return A.nb <= 2 ? launch_mindiv_eng<kEng, true, 2>(A, nbp, lds, s)
+                   : launch_mindiv_eng<kEng, true, kMaxBands>(A, nbp, lds, s);
 }
 
 hipError_t launch_mindiv(const DevModel* M, const uint16_t* const* hist, int nb, int engine,
@@ -1610,9 +1630,9 @@ hipError_t launch_mindiv(const DevModel* M, const uint16_t* const* hist, int nb,
   const int lds_max = M[0].lds_max > 0 ? M[0].lds_max : 65536;
   if (lds > (size_t)lds_max) return hipErrorInvalidValue;
   switch (engine) {
-    case kEngValu: return msl ? launch_mindiv_eng<kEngValu, true>(A, nbp, lds, s) : launch_mindiv_eng<kEngValu, false>(A, nbp, lds, s);
-    case kEngMfma16: return msl ? launch_mindiv_eng<kEngMfma16, true>(A, nbp, lds, s) : launch_mindiv_eng<kEngMfma16, false>(A, nbp, lds, s);
-    case kEngMfma16x2: return msl ? launch_mindiv_eng<kEngMfma16x2, true>(A, nbp, lds, s) : launch_mindiv_eng<kEngMfma16x2, false>(A, nbp, lds, s);
+    case kEngValu: return launch_mindiv_bands<kEngValu>(A, msl, nbp, lds, s);
+    case kEngMfma16: return launch_mindiv_bands<kEngMfma16>(A, msl, nbp, lds, s);
+    case kEngMfma16x2: return launch_mindiv_bands<kEngMfma16x2>(A, msl, nbp, lds, s);
   }
   return hipErrorInvalidValue;
 }
