@@ -1260,9 +1260,8 @@ __global__ void __launch_bounds__(256) k_mindiv(MindivArgs A) {
     const ushort2 m23 = __builtin_elementwise_max(ushort2{u[4], u[5]}, ushort2{u[6], u[7]});
     vmax = __builtin_elementwise_max(vmax, __builtin_elementwise_max(m01, m23));
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      vfrac |= __builtin_bit_cast(unsigned, half2{(_Float16)__builtin_amdgcn_fracth(v[2 * q]),
-                                                  (_Float16)__builtin_amdgcn_fracth(v[2 * q + 1])});
+    for (int q = 0; q < 8; ++q)
+      vfrac |= (unsigned)__builtin_bit_cast(unsigned short, (_Float16)__builtin_amdgcn_fracth(v[q]));
     const half2 one2 = {(_Float16)1.f, (_Float16)1.f};
 #pragma unroll
     for (int q = 0; q < 4; ++q) kv = __builtin_amdgcn_fdot2(half2{v[2 * q], v[2 * q + 1]}, one2, kv, false);
