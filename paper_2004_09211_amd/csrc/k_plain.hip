@@ -280,6 +280,30 @@ hipError_t launch_step_pirf(const DevModel& M, const StepIO& io, bool from_hist,
 // held to the grid's span.
 constexpr float kGaussTail2 = 40.f;  // log2 units: truncation of the Gaussian terms
 
+// Sum over all 64 lanes (every lane active), the same value in every lane
+// and bit for bit the result of the xor butterfly over lane masks 1..32:
+// within each 16-lane row the pair, quad, half-row and row steps are DPP
+// moves (after the quad step every lane of a quad holds the same value, so
+// the mirrored partner adds the same operand as the xor partner), then the
+// four row sums are added as (r0 + r1) + (r2 + r3), the butterfly's order.
+// No LDS round trip: the fixed point below is bound by this latency.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float wave_sum64(float x) {
+  x += dpp_move<0xb1>(x);   // quad_perm [1,0,3,2]: lane ^ 1
+  x += dpp_move<0x4e>(x);   // quad_perm [2,3,0,1]: lane ^ 2
+  x += dpp_move<0x141>(x);  // row_half_mirror: the other quad of the 8
+  x += dpp_move<0x140>(x);  // row_mirror: the other 8 of the row
+  const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 0));
+  const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 16));
+  const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 32));
+  const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 48));
+  return (r0 + r1) + (r2 + r3);
+}
+
 __global__ void __launch_bounds__(256) k_gauss_mindiv(DevModel M, const int32_t* __restrict__ row_ptr,
                                                       const int16_t* __restrict__ toa, float a, float amp,
                                                       float* __restrict__ depth, float* __restrict__ value,
@@ -347,8 +371,8 @@ __global__ void __launch_bounds__(256) k_gauss_mindiv(DevModel M, const int32_t*
         a1 = fmaf(w, e, a1);
       }
     }
-    s0 = group_sum<1, 32>(a0);
-    s1 = group_sum<1, 32>(a1);
+    s0 = wave_sum64(a0);
+    s1 = wave_sum64(a1);
   };
   if (K > 0.f) {
     for (int it = 0; it < 200; ++it) {
@@ -356,7 +380,12 @@ __global__ void __launch_bounds__(256) k_gauss_mindiv(DevModel M, const int32_t*
       sums(d, S0, s1);
       if (!(S0 > 0.f)) break;
       const float step = s1 / S0;
-      d += step;
+      // a step that leaves d unchanged in fp32 (below half its spacing,
+      // which exceeds 1e-5 from 256 bins on) would repeat itself to the last
+      // iteration: stopping here gives the same d
+      const float dn = d + step;
+      if (dn == d) break;
+      d = dn;
       if (fabsf(step) <= 1e-5f) break;
     }
     d = fminf(fmaxf(d, (float)M.d_lo), (float)dhi);
