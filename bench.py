@@ -772,8 +772,8 @@ class OracleLeg:
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp16x2", choices=["fp32", "fp16", "fp16x2"])
     ap.add_argument("--frames", type=int, default=30)
     ap.add_argument("--plain-steps", type=int, default=1)
