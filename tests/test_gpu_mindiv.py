@@ -187,6 +187,28 @@ def test_min_divergence_msl_matches_oracle(lib, prec, nb):
     assert int(am[5]) == 0 and float(val[5]) == 0.0
 
 
+def test_min_divergence_msl_full_size_sampled(lib):
+    """Two bands at the benchmark's size, as the benchmark times them: frames
+    0 and 1 of the 256x256, T = 4096 workload, the second band with a
+    sigma = 4 Gaussian IRF of the same taps. Every pixel on the GPU; 256
+    sampled pixels (corners, edges, object boundaries, random) against the
+    oracle's multispectral objective, split fp16 engine."""
+    wl = synth.config4(device=DEV, frames=2)
+    p2 = dict(wl.params(), irf=synth.gaussian_irf(4.0, wl.W, wl.c))
+    ctxs = [lib.Context(wl.params(), "fp16x2"), lib.Context(p2, "fp16x2")]
+    am, val = lib.min_divergence_msl(ctxs, [wl.hist[0], wl.hist[1]])
+    assert all(c.last_device_status() == 0 for c in ctxs)
+    rng = np.random.default_rng(4)
+    pix = np.unique(np.concatenate([rng.choice(wl.P, 240, replace=False),
+                                    [0, 255, wl.P - 256, wl.P - 1, 40 * 256 + 20,
+                                     40 * 256 + 19, 180 * 256 + 168, 100 * 256 + 100]]))
+    models = [oracle.Model.from_params(wl.params()), oracle.Model.from_params(p2)]
+    zs = [frame_hist(wl.hist[0], wl.T, pix), frame_hist(wl.hist[1], wl.T, pix)]
+    J = oracle.msl_objective(zs, models)
+    tol = 2 * (2.0 * cost_err("fp16x2") + 4e-5) + 1e-5
+    check_argmax(am.cpu().numpy()[pix] - wl.d_lo, J, val.cpu().numpy()[pix], tol, "msl full size")
+
+
 def test_min_divergence_msl_one_band_equals_single(lib):
     """One band: argmax of log(c/K) is the argmax of ell (the same first
     maximiser), and value = log(ell * beta / (beta+1)) - log K."""
