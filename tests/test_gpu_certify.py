@@ -1,8 +1,8 @@
 """Parity at full size, state-forced: the benchmark's configuration (256x256
 pixels, T = 4096 fp16 histograms, 30 frames of the moving scene, the split
 fp16 matrix-core engine, and the fp32 vector engine on three frames) and the
-128x128 x 50-frame photon-list video (plain, and with presence
-probabilities and faulty pixels).
+128x128 x 50-frame photon-list video (plain, with presence probabilities
+and faulty pixels, and with a Gaussian IRF of its own for every pixel).
 
 The GPU runs its own chain over all 30 frames (one step call per frame).
 At frames 0, 1, 2, 10, 20, 28 and 29 the GPU's input state (fp32, cast to
@@ -165,3 +165,43 @@ def test_full_size_video_state_forced(lib, case, frames):
         rep = compare(sub, ref, model=model, state=s_in, z=z, pixels=pix, mean_rel=1e-4,
                       var_rel=1e-3, int_rel=1e-3, faulty=fl, label=f"video {case} frame {n}")
         print("video", case, n, len(pix), rep, flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_video_pirf_state_forced(lib):
+    """The same video with every pixel its own Gaussian IRF (sigma uniform on
+    [2.5, 3.5] bins, 31 taps; Sec. II-A), as the per-pixel-IRF entry point is
+    timed: the GPU runs its chain over all 50 frames; at frames 1, 25 and 49
+    the sampled pixels are stepped by the oracle from the GPU's input state
+    with the same IRFs. Near ties (oracle margin <= 1e-3) may take another
+    grid depth; everything else at the stated tolerances."""
+    wl = synth.config2()
+    model = oracle.Model.from_params(wl.params())
+    rng = np.random.default_rng(5)
+    irf_pix = np.stack([synth.gaussian_irf(s, wl.W, wl.c) for s in rng.uniform(2.5, 3.5, wl.P)])
+    frames = (1, 25, 49)
+    ctx = lib.Context(wl.params())
+    st = [lib.State.empty(wl.P, DEV), lib.State.empty(wl.P, DEV)]
+    ctx.state_init(st[0])
+    out = lib.Outputs.empty(wl.P, DEV)
+    irf_d = torch.as_tensor(irf_pix, device=DEV)
+    saved = {}
+    for n, f in enumerate(wl.frames):
+        prev, nxt = st[n % 2], st[(n + 1) % 2]
+        if n in frames:
+            s_in = oracle.State(*(t.double().cpu().numpy() for t in (prev.m, prev.v, prev.pi, prev.b)))
+        ctx.step_pirf((f.row_ptr.to(DEV), f.toa.to(DEV)), irf_d, prev, nxt, out)
+        if n in frames:
+            g = gpu_outputs_np(out)
+            g["mean"] = nxt.m.cpu().numpy()
+            saved[n] = (s_in, g)
+    assert ctx.last_device_status() == 0
+    rng = np.random.default_rng(78)
+    for n in frames:
+        s_in, g = saved[n]
+        pix = sample_pixels(wl, n, rng)
+        z = frame_hist(wl.frames[n], wl.T, pix)
+        _, ref = oracle.step(model, s_in, z, pixels=pix, irf_pix=irf_pix)
+        sub = {k: v[pix] for k, v in g.items()}
+        rep = compare(sub, ref, mean_rel=1e-4, var_rel=1e-3, int_rel=1e-3, label=f"video pirf frame {n}")
+        print("video pirf", n, len(pix), rep, flush=True)
